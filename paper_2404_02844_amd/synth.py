@@ -1,0 +1,226 @@
+"""Seeded synthetic inputs for phase-insensitive detector tomography.
+
+Produces what a tomography experiment hands the solver -- probe mean photon numbers
+mu_d and measured outcome frequencies P[d, n] -- together with the known detector
+POVM Pi_true that generated them.  Nothing here implements the reconstruction: the
+forward model used to sample P calls ``scipy.stats.poisson`` (a library routine), so
+this module shares no arithmetic with either the CPU oracle or the HIP kernels.  Both
+sides receive the same arrays from here.
+
+Detector model (a click detector with B bins, outcome n = number of clicked bins,
+N = B + 1 outcomes; the paper's detector is a multiplexed click counter, Sec. 2.2):
+
+* dark counts: each bin clicks by itself with probability ``dark``; the chain of
+  clicked-bin counts starts from Binomial(B, dark);
+* every incident photon is detected with probability ``eta`` and lands in a
+  uniformly chosen bin, so k clicked bins become k + 1 with probability
+  eta * (B - k) / B;
+* optional crosstalk: each primary click triggers each of its two neighbours with
+  probability x if that neighbour is idle, modelled at the count level as
+  k -> min(B, k + Binomial(2k, x (B - k) / (B - 1))).
+
+Probe states are coherent states with mean photon numbers mu_d on a linear grid
+(Eq. Fmatrix gives their photon-number distribution, a Poisson pmf).  Outcome
+frequencies are multinomial samples of q_d = sum_m Poisson(m; mu_d) Pi_true[m, :]
+with a fixed number of shots per probe.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+from scipy import stats
+
+SEED_BASE = 240402844
+
+TRUNCATE = 0  # F_{d,m} = Poisson(m; mu_d) for m < M (Eq. Fmatrix as printed)
+LUMP = 1  # as TRUNCATE, but column M-1 carries the whole tail P(X >= M-1)
+
+
+@dataclasses.dataclass
+class Instance:
+    """One tomography problem: inputs (mu, P, gamma, ...) plus the generating POVM."""
+
+    name: str
+    M: int
+    N: int
+    D: int
+    mu: np.ndarray  # [D] float64, non-decreasing
+    P: np.ndarray  # [D, N] float64, rows sum to 1
+    Pi_true: np.ndarray  # [M, N] float64, rows on the simplex
+    gamma: float
+    tail_mode: int
+    threshold: float  # pmf threshold tau of the F band (0 -> dense)
+    shots: float
+    seed: int
+    detector: dict
+
+
+def rng_for(k: int, spawn: Optional[int] = None) -> np.random.Generator:
+    """PCG64 stream for config index k (and optionally its spawn-th child)."""
+    ss = np.random.SeedSequence(SEED_BASE + k)
+    if spawn is not None:
+        ss = ss.spawn(spawn + 1)[spawn]
+    return np.random.Generator(np.random.PCG64(ss))
+
+
+def _chain_matrix(B: int, eta: float) -> np.ndarray:
+    """One-photon transition matrix of the clicked-bin count (row-stochastic)."""
+    k = np.arange(B + 1, dtype=np.float64)
+    up = eta * (B - k) / B
+    T = np.diag(1.0 - up)
+    T[np.arange(B), np.arange(1, B + 1)] = up[:B]
+    return T
+
+
+def _crosstalk_matrix(B: int, x: float) -> np.ndarray:
+    C = np.zeros((B + 1, B + 1))
+    for k in range(B + 1):
+        if k == 0 or x <= 0.0 or B < 2:
+            C[k, k] = 1.0
+            continue
+        p = x * (B - k) / (B - 1)
+        j = np.arange(2 * k + 1)
+        w = stats.binom.pmf(j, 2 * k, p)
+        for jj, ww in zip(j, w):
+            C[k, min(B, k + jj)] += ww
+    return C
+
+
+def click_detector_povm(M: int, B: int, eta: float, dark: float = 0.0,
+                        crosstalk: float = 0.0, block: int = 128) -> np.ndarray:
+    """Pi_true[m, k] = P(k bins clicked | m photons), m in [0, M), k in [0, B]."""
+    T = _chain_matrix(B, eta)
+    pows = np.empty((block, B + 1, B + 1))
+    pows[0] = np.eye(B + 1)
+    for j in range(1, block):
+        pows[j] = pows[j - 1] @ T
+    step = pows[block - 1] @ T  # T^block
+    out = np.empty((M, B + 1))
+    row = stats.binom.pmf(np.arange(B + 1), B, dark) if dark > 0 else np.eye(B + 1)[0]
+    for m0 in range(0, M, block):
+        n = min(block, M - m0)
+        out[m0:m0 + n] = np.einsum("k,jkl->jl", row, pows[:n])
+        row = row @ step
+    if crosstalk > 0:
+        out = out @ _crosstalk_matrix(B, crosstalk)
+    out = np.clip(out, 0.0, None)
+    out /= out.sum(axis=1, keepdims=True)
+    return out
+
+
+def _probe_window(mu: float, lo_cap: int, hi_cap: int) -> tuple[int, int]:
+    s = math.sqrt(max(mu, 1.0))
+    lo = max(0, int(math.floor(mu - 12.0 * s - 40)))
+    hi = min(hi_cap, int(math.ceil(mu + 12.0 * s + 40)))
+    return max(lo, lo_cap), hi
+
+
+def outcome_probs(mu: np.ndarray, Pi_ext: np.ndarray, M: int, tail_mode: int) -> np.ndarray:
+    """q_d = sum_m Poisson(m; mu_d) Pi_true[m, :] (scipy pmf; data generation only).
+
+    LUMP: rows m >= M-1 of the detector are represented by row M-1 (tail mass on it).
+    TRUNCATE: Pi_ext must extend far enough past M that the Poisson tail is negligible;
+    the physical detector is defined for every photon number.
+    """
+    D = mu.shape[0]
+    N = Pi_ext.shape[1]
+    q = np.zeros((D, N))
+    last = Pi_ext.shape[0] - 1
+    for d in range(D):
+        m_ = float(mu[d])
+        if m_ == 0.0:
+            q[d] = Pi_ext[0]
+            continue
+        if tail_mode == LUMP:
+            lo, hi = _probe_window(m_, 0, M - 2)
+            if lo <= hi:
+                ms = np.arange(lo, hi + 1)
+                q[d] = stats.poisson.pmf(ms, m_) @ Pi_ext[lo:hi + 1]
+            q[d] += stats.poisson.sf(M - 2, m_) * Pi_ext[M - 1]
+        else:
+            lo, hi = _probe_window(m_, 0, last)
+            ms = np.arange(lo, hi + 1)
+            q[d] = stats.poisson.pmf(ms, m_) @ Pi_ext[lo:hi + 1]
+    q = np.clip(q, 0.0, None)
+    return q / q.sum(axis=1, keepdims=True)
+
+
+def sample_outcomes(q: np.ndarray, shots: float, rng: np.random.Generator) -> np.ndarray:
+    """P_d = Multinomial(shots, q_d) / shots."""
+    counts = rng.multinomial(int(shots), q)
+    return counts.astype(np.float64) / float(shots)
+
+
+def make_instance(name: str, *, M: int, B: int, eta: float, D: int, mu_max: float,
+                  shots: float, gamma: float, tail_mode: int, threshold: float,
+                  dark: float = 0.0, crosstalk: float = 0.0,
+                  rng: np.random.Generator, seed: int = 0, n_pad_to: Optional[int] = None,
+                  noiseless: bool = False) -> Instance:
+    N = B + 1
+    mu = np.linspace(0.0, mu_max, D)
+    if tail_mode == TRUNCATE:
+        ext = int(math.ceil(mu_max + 14.0 * math.sqrt(max(mu_max, 1.0)) + 60))
+        Pi_ext = click_detector_povm(max(M, ext + 1), B, eta, dark, crosstalk)
+    else:
+        Pi_ext = click_detector_povm(M, B, eta, dark, crosstalk)
+    q = outcome_probs(mu, Pi_ext, M, tail_mode)
+    P = q.copy() if noiseless else sample_outcomes(q, shots, rng)
+    Pi_true = Pi_ext[:M].copy()
+    if n_pad_to is not None and n_pad_to > N:
+        P = np.concatenate([P, np.zeros((D, n_pad_to - N))], axis=1)
+        Pi_true = np.concatenate([Pi_true, np.zeros((M, n_pad_to - N))], axis=1)
+        N = n_pad_to
+    return Instance(name=name, M=M, N=N, D=D, mu=mu, P=np.ascontiguousarray(P),
+                    Pi_true=np.ascontiguousarray(Pi_true), gamma=gamma, tail_mode=tail_mode,
+                    threshold=threshold, shots=shots, seed=seed,
+                    detector=dict(B=B, eta=eta, dark=dark, crosstalk=crosstalk))
+
+
+# --- the five workloads -------------------------------------------------------------
+
+def c1_small(seed_offset: int = 0) -> Instance:
+    """8-bin click detector, M=64, N=9, D=80 probes on mu in [0, 40], dense F."""
+    return make_instance("c1_m64_n9_d80", M=64, B=8, eta=0.9, D=80, mu_max=40.0,
+                         shots=1e6, gamma=1e-3, tail_mode=TRUNCATE, threshold=0.0,
+                         rng=rng_for(1 + seed_offset), seed=SEED_BASE + 1 + seed_offset)
+
+
+def c2_medium(seed_offset: int = 0) -> Instance:
+    """64-bin detector, M=4096, N=65, D=5000 probes on mu in [0, 4500], band tau=1e-16."""
+    return make_instance("c2_m4096_n65_d5000", M=4096, B=64, eta=0.85, dark=1e-4, D=5000,
+                         mu_max=4500.0, shots=1e7, gamma=1e-4, tail_mode=LUMP, threshold=1e-16,
+                         rng=rng_for(2 + seed_offset), seed=SEED_BASE + 2 + seed_offset)
+
+
+def c3_mega(M: int = 1_000_000, D: int = 100_000) -> Instance:
+    """99-bin detector with 1% crosstalk, M=1e6, N=100, D=1e5 probes on mu in [0, 1.1M]."""
+    return make_instance(f"c3_m{M}_n100_d{D}", M=M, B=99, eta=0.8, crosstalk=0.01, D=D,
+                         mu_max=1.1 * M, shots=1e8, gamma=1e-5, tail_mode=LUMP, threshold=1e-16,
+                         rng=rng_for(3), seed=SEED_BASE + 3)
+
+
+def random_detector(rng: np.random.Generator, M: int, *, bins=(8, 128), eta=(0.5, 0.95),
+                    dark=(0.0, 1e-3), crosstalk=(0.0, 0.0), n_pad_to=None, shots=1e7,
+                    gamma=1e-4, name="rand") -> Instance:
+    """One detector of the batched / warm-start families (D = round(1.2 M), mu to 1.1 M)."""
+    B = int(rng.integers(bins[0], bins[1] + 1))
+    e = float(rng.uniform(*eta))
+    dk = float(rng.uniform(*dark))
+    xt = float(rng.uniform(*crosstalk)) if crosstalk[1] > 0 else 0.0
+    D = int(round(1.2 * M))
+    return make_instance(name, M=M, B=B, eta=e, dark=dk, crosstalk=xt, D=D, mu_max=1.1 * M,
+                         shots=shots, gamma=gamma, tail_mode=LUMP, threshold=1e-16, rng=rng,
+                         n_pad_to=n_pad_to)
+
+
+def c4_batch(count: int = 256, m_range=(256, 8192)) -> list[Instance]:
+    """Batch of independent detectors with uneven M and N (seeded spawn streams)."""
+    out = []
+    for i in range(count):
+        rng = rng_for(4, spawn=i)
+        M = int(rng.integers(m_range[0], m_range[1] + 1))
+        out.append(random_detector(rng, M, name=f"c4_{i}"))
+    return out

@@ -1,0 +1,137 @@
+"""Pins of the oracle's solver (accelerated projected gradient with restart) and certificates."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import certify, fista, objective, poisson, simplex
+from paper_2404_02844_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def c1():
+    inst = synth.c1_small()
+    F, lo, hi = poisson.build_F(inst.mu, inst.M, inst.threshold, inst.tail_mode)
+    return inst, F
+
+
+def test_lipschitz_is_the_top_eigenvalue(c1):
+    inst, F = c1
+    Fd = F.toarray()
+    M = inst.M
+    Lm = np.diag(np.r_[1.0, np.full(M - 2, 2.0), 1.0]) - np.eye(M, k=1) - np.eye(M, k=-1)
+    H = 2 * Fd.T @ Fd + 2 * inst.gamma * Lm
+    lam = np.linalg.eigvalsh(H)[-1]
+    assert fista.lipschitz(F, inst.gamma, M) == pytest.approx(1.05 * lam, rel=1e-9)
+
+
+def test_monotone_and_converging(c1):
+    inst, F = c1
+    L = fista.lipschitz(F, inst.gamma, inst.M)
+    r = fista.fista_r(F, inst.P, inst.gamma, L, 600)
+    assert np.all(np.diff(r.history) <= 0)
+    Xs = r.X
+    assert np.all(Xs >= 0) and np.max(np.abs(Xs.sum(1) - 1)) < 1e-14
+    k1 = certify.kkt_residual(F, inst.P, fista.fista_r(F, inst.P, inst.gamma, L, 100).X, inst.gamma)
+    k2 = certify.kkt_residual(F, inst.P, Xs, inst.gamma)
+    assert k2 < k1
+
+
+def test_polished_optimum_and_bounds(c1):
+    inst, F = c1
+    with open(os.path.join(GOLDEN, "c1_oracle.json")) as fh:
+        gold = json.load(fh)
+    L = fista.lipschitz(F, inst.gamma, inst.M)
+    assert L == pytest.approx(gold["L_hat"], rel=1e-13)
+    r = fista.fista_r(F, inst.P, inst.gamma, L, 2000)
+    assert r.f == pytest.approx(gold["f_2000"], rel=1e-12)
+    fstar = gold["f_star"]
+    # optimum certified by sign checks of the polished active-set solution
+    assert gold["polish_certified"]
+    # Frank-Wolfe gap bounds the suboptimality
+    assert certify.fw_gap(F, inst.P, r.X, inst.gamma) >= r.f - fstar
+    assert r.f >= fstar * (1 - 1e-14)
+    # the KKT residual of the polished point is at rounding level
+    Xstar = np.array(gold["Pi_star"])
+    assert certify.kkt_residual(F, inst.P, Xstar, inst.gamma) < 1e-12
+    assert objective.objective(F, inst.P, Xstar, inst.gamma) == pytest.approx(fstar, rel=1e-13)
+
+
+def test_single_outcome_is_trivial():
+    mu = np.linspace(0, 10, 12)
+    F = poisson.dense_F(mu, 16, 0.0, poisson.TRUNCATE)
+    P = np.ones((12, 1))
+    r = fista.fista_r(F, P, 0.1, fista.lipschitz(F, 0.1, 16), 5)
+    assert np.array_equal(r.X, np.ones((16, 1)))
+
+
+def test_vacuum_probe_spreads_by_regulariser():
+    # one probe with mu = 0 sees only m = 0; with gamma > 0 every row must equal P_0
+    M, N = 12, 4
+    F = poisson.dense_F(np.array([0.0]), M, 0.0, poisson.TRUNCATE)
+    assert np.array_equal(F[0], np.eye(M)[0])
+    P0 = np.array([[0.1, 0.2, 0.3, 0.4]])
+    L = fista.lipschitz(F, 1.0, M)
+    r = fista.fista_r(F, P0, 1.0, L, 5000)
+    assert np.max(np.abs(r.X - P0)) < 1e-8
+
+
+def test_huge_gamma_objective_prefers_constant_columns():
+    # For Pi = 1 c^T the regulariser vanishes and f(c) = ||s c^T - P||^2 with s = F 1, whose
+    # minimiser over the simplex is c* = P_S(P^T s / ||s||^2).
+    mu = np.linspace(0, 10, 15)
+    M, N = 20, 5
+    F = poisson.dense_F(mu, M, 0.0, poisson.TRUNCATE)
+    rng = np.random.default_rng(5)
+    P = simplex.project_rows(rng.random((15, N)))
+    s = F @ np.ones(M)
+    cstar = simplex.project_simplex(P.T @ s / (s @ s))
+    fstar = objective.objective(F, P, np.outer(np.ones(M), cstar), 1e6)
+    for _ in range(50):
+        c = simplex.project_simplex(rng.normal(size=N))
+        assert objective.objective(F, P, np.outer(np.ones(M), c), 1e6) >= fstar - 1e-15
+
+
+def test_noiseless_recovery_tiny():
+    # M=12, N=4 detector, D=40 probes on [0, 12]: Poisson inversion is ill-posed
+    # (cond(F) ~ 4e5), so recovery is pinned at the accuracy that conditioning allows.
+    M, B = 12, 3
+    Pi_true = synth.click_detector_povm(M, B, 0.7)
+    mu = np.linspace(0, 12, 40)
+    F = poisson.dense_F(mu, M, 0.0, poisson.TRUNCATE)
+    P = F @ Pi_true
+    L = fista.lipschitz(F, 0.0, M)
+    r = fista.fista_r(F, P, 0.0, L, 40000, exact_sums=False)
+    assert r.f <= 1e-12 * np.sum(P * P)
+    fids = [certify.fidelity(r.X[:, n], Pi_true[:, n]) for n in range(B + 1)]
+    assert min(fids) >= 0.998
+    assert np.max(np.abs(r.X - Pi_true)) <= 1e-2
+
+
+def test_fidelity_closed_forms():
+    a = np.array([0.1, 0.5, 0.4])
+    assert certify.fidelity(a, a) == pytest.approx(1.0, rel=1e-15)
+    assert certify.fidelity(a, 3 * a) == pytest.approx(1.0, rel=1e-15)
+    assert certify.fidelity(np.array([1.0, 0, 0]), np.array([0, 1.0, 0])) == 0.0
+    # two-level case by hand: sqrt(.5*.2)+sqrt(.5*.8) = .3162+.6325; squared / (1*1)
+    assert certify.fidelity(np.array([0.5, 0.5]), np.array([0.2, 0.8])) == pytest.approx(
+        (math.sqrt(0.1) + math.sqrt(0.4)) ** 2, rel=1e-15)
+
+
+def test_kkt_detects_a_planted_mistake(c1):
+    # moving mass inside a row of the optimum makes the KKT residual jump
+    inst, F = c1
+    with open(os.path.join(GOLDEN, "c1_oracle.json")) as fh:
+        gold = json.load(fh)
+    X = np.array(gold["Pi_star"])
+    k0 = certify.kkt_residual(F, inst.P, X, inst.gamma)
+    Y = X.copy()
+    i = 30
+    j = int(np.argmax(Y[i]))
+    Y[i, j] -= 0.01
+    Y[i, (j + 1) % Y.shape[1]] += 0.01
+    assert certify.kkt_residual(F, inst.P, Y, inst.gamma) > 1e3 * max(k0, 1e-16)

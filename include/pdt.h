@@ -1,0 +1,169 @@
+/*
+ * pdt.h -- C ABI of libpdt, an MI355X (gfx950) solver for phase-insensitive quantum
+ * detector tomography (arXiv 2404.02844).
+ *
+ * Problem (Eq. min, Sec. 2.1, with the regulariser of Eq. regul, Sec. 3.2):
+ *
+ *     minimise   f(Pi) = ||F Pi - P||_F^2 + gamma * sum_n sum_{i<M-1} (Pi[i][n] - Pi[i+1][n])^2
+ *     subject to Pi[i][n] >= 0,  sum_n Pi[i][n] = 1  for every photon number i,
+ *
+ * where Pi is the M x N POVM matrix (row i = photon number i, column n = outcome n),
+ * P is the D x N matrix of measured outcome frequencies, and F is the D x M matrix of
+ * coherent-probe photon-number distributions F[d][i] = mu_d^i exp(-mu_d) / i!
+ * (Eq. Fmatrix).  F is never stored: the kernels regenerate it in its band, the
+ * photon numbers where F[d][i] >= pmf_threshold.
+ *
+ * The solver is an accelerated projected-gradient method: a gradient step, the
+ * row-wise Euclidean projection onto the probability simplex P_{S^M} (Eq. Mp1_proj,
+ * App. B.1) and Nesterov momentum with a monotone restart (a rejected step resets the
+ * momentum).  It is the first-order analogue of the paper's first stage (Algorithm 2).
+ *
+ * Conventions.  Every call returns a pdt_status; nothing throws across the ABI.  On a
+ * non-OK status pdt_last_error() returns a thread-local message.  Matrices are dense
+ * row-major FP64 at the boundary.  "device" pointers are HIP device memory on the
+ * problem's device; "host" pointers are ordinary host memory.  The caller keeps
+ * ownership of every array it passes; the library copies what it needs.  Calls that
+ * take a stream enqueue their work on it and return after it has completed.
+ */
+#ifndef PDT_H
+#define PDT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pdt_problem_s* pdt_problem_t;
+
+typedef enum {
+  PDT_OK = 0,
+  PDT_ERR_INVALID_ARG = 1,   /* bad sizes, NaN/Inf, mu < 0 or decreasing, gamma < 0, ... */
+  PDT_ERR_OUT_OF_MEMORY = 2, /* a device allocation failed; nothing is leaked */
+  PDT_ERR_DEVICE = 3,        /* a HIP runtime call or kernel launch failed */
+  PDT_ERR_NOT_CONVERGED = 4, /* max_iters reached before the requested tolerance */
+  PDT_ERR_NUMERIC = 5        /* the objective became NaN/Inf */
+} pdt_status;
+
+typedef enum {
+  PDT_FP64 = 0,       /* products and iterates in FP64 (FP64 MFMA) */
+  PDT_FP32 = 1,       /* products and iterates in FP32 (FP32 MFMA), FP64 objective */
+  PDT_MIXED_BF16 = 2  /* reserved: BF16 products with FP32 accumulation + FP64 refinement */
+} pdt_precision;
+
+typedef enum {
+  PDT_TAIL_TRUNCATE = 0, /* F[d][i] = Poisson(i; mu_d) for i < M, as printed in Eq. Fmatrix */
+  PDT_TAIL_LUMP = 1      /* as TRUNCATE, but column M-1 holds P(X >= M-1): rows of F sum to 1 */
+} pdt_tail_mode;
+
+typedef enum {
+  PDT_INIT_UNIFORM = 0, /* Pi = 1/N (the paper's start, Algorithm 1) */
+  PDT_INIT_USER = 1     /* start from the caller's Pi, projected onto the constraints first */
+} pdt_init_mode;
+
+/* One tomography instance (arguments follow Eq. min and Eq. Fmatrix). */
+typedef struct {
+  int64_t M;            /* Hilbert-space cutoff: photon numbers 0..M-1, M >= 1 */
+  int64_t N;            /* detector outcomes, 1 <= N <= 192 */
+  int64_t D;            /* probe states, D >= 1 */
+  const double* mu;     /* host [D]: probe mean photon numbers |alpha_d|^2, finite, >= 0,
+                           non-decreasing */
+  const double* P;      /* [D*N] row-major outcome frequencies, finite, >= 0 (host memory,
+                           or device memory when P_on_device != 0) */
+  int P_on_device;
+  double gamma;         /* regularisation weight of Eq. regul, finite, >= 0 */
+  double pmf_threshold; /* keep F entries >= this (0: dense F), finite, in [0, 1) */
+  int tail_mode;        /* pdt_tail_mode */
+} pdt_problem_desc;
+
+/*
+ * Validates every instance, copies mu and P to device memory owned by the problem,
+ * computes the F bands (per probe: first/last photon number with F >= threshold, and
+ * the lumped tail mass) and the Lipschitz constant L = 1.05 * lambda_max(2 F^T F +
+ * 2 gamma L_path) of the gradient by 100 FP64 power iterations.  stream: a hipStream_t
+ * (NULL = the default stream); all later calls on the problem use it.  On error
+ * nothing is allocated and *out is set to NULL.  n_instances must be 1 (reserved for
+ * batches).
+ */
+pdt_status pdt_make_problem(const pdt_problem_desc* descs, int64_t n_instances, void* stream,
+                            pdt_problem_t* out);
+
+/* Frees all device memory of the problem.  NULL is a no-op. */
+void pdt_destroy_problem(pdt_problem_t problem);
+
+typedef struct {
+  int precision;          /* pdt_precision */
+  int init;               /* pdt_init_mode */
+  int64_t max_iters;      /* iterations of the momentum method, >= 0 */
+  double rel_obj_tol;     /* stop once f - f_star <= rel_obj_tol * f_star (needs f_star > 0) */
+  double f_star;          /* known optimum value; <= 0 disables the tolerance test */
+  double step_L;          /* step = 1 / step_L; 0 uses the problem's own Lipschitz estimate */
+  double* history;        /* optional device [max_iters]: f after each iteration (FP64) */
+} pdt_solve_opts;
+
+typedef struct {
+  int64_t iters;          /* iterations performed */
+  int64_t rejects;        /* candidate steps rejected (momentum restarts) */
+  double objective;       /* f at the returned Pi, FP64 */
+  double kkt;             /* KKT residual of App. B with lambda_i = -min_n df/dPi[i][n] */
+  double L_used;          /* Lipschitz constant used for the step */
+  double seconds;         /* wall time of the call */
+  int converged;          /* 1 if the tolerance test was met */
+} pdt_solve_info;
+
+/*
+ * Solves instance 0.  Pi: device [M*N] row-major FP64; read when init == USER, always
+ * overwritten with the final iterate (rows on the simplex).  Returns
+ * PDT_ERR_NOT_CONVERGED (with Pi and info filled) when a tolerance was requested and
+ * max_iters ran out first.
+ */
+pdt_status pdt_solve(pdt_problem_t problem, double* Pi, const pdt_solve_opts* opts,
+                     pdt_solve_info* info);
+
+/*
+ * f(Pi) (FP64) and optionally its gradient 2 F^T (F Pi - P) + 2 gamma L_path Pi
+ * (Table "ops": objective value and gradient).  Pi: device [M*N]; grad_out: device
+ * [M*N] or NULL; f_out: host.  Pi is used as given (not projected).
+ */
+pdt_status pdt_objective(pdt_problem_t problem, const double* Pi, double* f_out, double* grad_out);
+
+/*
+ * KKT residual of App. B at Pi (device [M*N]): sqrt(mean((Pi * (grad + lambda))^2))
+ * with lambda_i = -min_n grad[i][n].  Result in *kkt_out (host).
+ */
+pdt_status pdt_kkt(pdt_problem_t problem, const double* Pi, double* kkt_out);
+
+/*
+ * Row-wise Euclidean projection onto the probability simplex, P_{S^M} of Eq. Mp1_proj:
+ * Y[r] = argmin_{y >= 0, sum y = 1} ||X[r] - y||.  X, Y: device [rows*cols] row-major
+ * FP64 (X == Y allowed); 1 <= cols <= 1024.  stream: hipStream_t or NULL.
+ */
+pdt_status pdt_project_simplex(const double* X, double* Y, int64_t rows, int64_t cols, void* stream);
+
+/* Same, FP32. */
+pdt_status pdt_project_simplex_f32(const float* X, float* Y, int64_t rows, int64_t cols, void* stream);
+
+/* Problem facts for tests and reports: band edges (host int32 [D] each, nullable),
+ * lumped tail mass (host [D], nullable), Lipschitz constant (host, nullable),
+ * number of band entries sum_d (hi_d - lo_d + 1) (host, nullable). */
+pdt_status pdt_problem_bands(pdt_problem_t problem, int32_t* lo, int32_t* hi, double* tail,
+                             double* lipschitz, int64_t* nnz);
+
+/*
+ * Measurement hook: enqueues `reps` launches of one kernel of the iteration on the
+ * problem's stream and returns without waiting, so the caller can bracket them with
+ * its own HIP events.  kernel: 0 = transposed band product + projected step,
+ * 1 = forward band product + objective partials, 2 = accept/reject decision,
+ * 3 = one whole iteration (0, 1, 2).  Requires an earlier pdt_solve in the same
+ * precision (it works on that solve's buffers, whose contents it overwrites).
+ */
+pdt_status pdt_replay_kernel(pdt_problem_t problem, int kernel, int precision, int64_t reps);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* pdt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDT_H */

@@ -1,0 +1,241 @@
+"""ctypes binding of libpdt (include/pdt.h): argument marshalling only.
+
+Every computation runs in the HIP library.  Device arrays are torch tensors on the
+GPU, passed by ``data_ptr()``; streams are torch's current HIP stream.  If the shared
+library is missing the binding raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpdt.so")
+
+PDT_OK = 0
+PDT_ERR_INVALID_ARG = 1
+PDT_ERR_OUT_OF_MEMORY = 2
+PDT_ERR_DEVICE = 3
+PDT_ERR_NOT_CONVERGED = 4
+PDT_ERR_NUMERIC = 5
+
+PDT_FP64 = 0
+PDT_FP32 = 1
+PDT_MIXED_BF16 = 2
+
+PDT_TAIL_TRUNCATE = 0
+PDT_TAIL_LUMP = 1
+
+PDT_INIT_UNIFORM = 0
+PDT_INIT_USER = 1
+
+STATUS_NAMES = {0: "PDT_OK", 1: "PDT_ERR_INVALID_ARG", 2: "PDT_ERR_OUT_OF_MEMORY", 3: "PDT_ERR_DEVICE",
+                4: "PDT_ERR_NOT_CONVERGED", 5: "PDT_ERR_NUMERIC"}
+
+
+class PdtError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class pdt_problem_desc(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int64), ("N", ctypes.c_int64), ("D", ctypes.c_int64),
+                ("mu", ctypes.POINTER(ctypes.c_double)), ("P", ctypes.c_void_p),
+                ("P_on_device", ctypes.c_int), ("gamma", ctypes.c_double),
+                ("pmf_threshold", ctypes.c_double), ("tail_mode", ctypes.c_int)]
+
+
+class pdt_solve_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("init", ctypes.c_int), ("max_iters", ctypes.c_int64),
+                ("rel_obj_tol", ctypes.c_double), ("f_star", ctypes.c_double), ("step_L", ctypes.c_double),
+                ("history", ctypes.c_void_p)]
+
+
+class pdt_solve_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int64), ("rejects", ctypes.c_int64), ("objective", ctypes.c_double),
+                ("kkt", ctypes.c_double), ("L_used", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("converged", ctypes.c_int)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2404_02844_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+        L.pdt_make_problem.argtypes = [ctypes.POINTER(pdt_problem_desc), i64, vp, ctypes.POINTER(vp)]
+        L.pdt_destroy_problem.argtypes = [vp]
+        L.pdt_destroy_problem.restype = None
+        L.pdt_solve.argtypes = [vp, vp, ctypes.POINTER(pdt_solve_opts), ctypes.POINTER(pdt_solve_info)]
+        L.pdt_objective.argtypes = [vp, vp, dp, vp]
+        L.pdt_kkt.argtypes = [vp, vp, dp]
+        L.pdt_project_simplex.argtypes = [vp, vp, i64, i64, vp]
+        L.pdt_project_simplex_f32.argtypes = [vp, vp, i64, i64, vp]
+        L.pdt_problem_bands.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), dp, dp,
+                                        ctypes.POINTER(ctypes.c_int64)]
+        L.pdt_replay_kernel.argtypes = [vp, ctypes.c_int, ctypes.c_int, i64]
+        L.pdt_replay_kernel.restype = ctypes.c_int
+        L.pdt_last_error.argtypes = []
+        L.pdt_last_error.restype = ctypes.c_char_p
+        for name in ("pdt_make_problem", "pdt_solve", "pdt_objective", "pdt_kkt", "pdt_project_simplex",
+                     "pdt_project_simplex_f32", "pdt_problem_bands"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def pdt_last_error() -> str:
+    return lib().pdt_last_error().decode()
+
+
+def _check(status: int, allow=()) -> int:
+    if status != PDT_OK and status not in allow:
+        raise PdtError(status, pdt_last_error())
+    return status
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _f64_host(a):
+    import numpy as np
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def pdt_make_problem(mu, P, M: int, gamma: float, pmf_threshold: float, tail_mode: int, stream=None):
+    """Create a problem from probe means ``mu`` [D] (host) and outcomes ``P`` [D, N]
+    (numpy array on the host, or a float64 torch tensor on the GPU)."""
+    mu_h = _f64_host(mu)
+    desc = pdt_problem_desc()
+    desc.M = int(M)
+    desc.D = int(mu_h.shape[0])
+    keep = [mu_h]
+    if hasattr(P, "data_ptr") and getattr(P, "is_cuda", False):
+        if str(P.dtype) != "torch.float64" or not P.is_contiguous():
+            raise ValueError("device P must be a contiguous float64 tensor")
+        desc.N = int(P.shape[1])
+        desc.P = ctypes.c_void_p(P.data_ptr())
+        desc.P_on_device = 1
+    else:
+        P_h = _f64_host(P)
+        keep.append(P_h)
+        desc.N = int(P_h.shape[1])
+        desc.P = P_h.ctypes.data_as(ctypes.c_void_p)
+        desc.P_on_device = 0
+    desc.mu = mu_h.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    desc.gamma = float(gamma)
+    desc.pmf_threshold = float(pmf_threshold)
+    desc.tail_mode = int(tail_mode)
+    out = ctypes.c_void_p()
+    stream_arg = ctypes.c_void_p(0) if stream == 0 else _stream_ptr(stream)
+    _check(lib().pdt_make_problem(ctypes.byref(desc), 1, stream_arg, ctypes.byref(out)))
+    return out
+
+
+def pdt_destroy_problem(handle) -> None:
+    if handle:
+        lib().pdt_destroy_problem(handle)
+
+
+def pdt_solve(handle, Pi, *, precision=PDT_FP64, init=PDT_INIT_UNIFORM, max_iters=1000, rel_obj_tol=0.0,
+              f_star=0.0, step_L=0.0, history=None, allow_not_converged=True) -> dict:
+    """Solve in place: ``Pi`` is a contiguous float64 [M, N] GPU tensor."""
+    o = pdt_solve_opts(precision=precision, init=init, max_iters=int(max_iters), rel_obj_tol=float(rel_obj_tol),
+                       f_star=float(f_star), step_L=float(step_L),
+                       history=ctypes.c_void_p(history.data_ptr()) if history is not None else None)
+    info = pdt_solve_info()
+    st = _check(lib().pdt_solve(handle, ctypes.c_void_p(Pi.data_ptr()), ctypes.byref(o), ctypes.byref(info)),
+                allow=(PDT_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+    d = info.as_dict()
+    d["status"] = st
+    return d
+
+
+def pdt_objective(handle, Pi, grad=None) -> float:
+    f = ctypes.c_double()
+    _check(lib().pdt_objective(handle, ctypes.c_void_p(Pi.data_ptr()), ctypes.byref(f),
+                               ctypes.c_void_p(grad.data_ptr()) if grad is not None else None))
+    return f.value
+
+
+def pdt_kkt(handle, Pi) -> float:
+    k = ctypes.c_double()
+    _check(lib().pdt_kkt(handle, ctypes.c_void_p(Pi.data_ptr()), ctypes.byref(k)))
+    return k.value
+
+
+def pdt_project_simplex(X, Y=None, stream=None):
+    """Row-wise simplex projection of a 2-D float64 or float32 GPU tensor."""
+    if Y is None:
+        Y = X.new_empty(X.shape)
+    rows, cols = int(X.shape[0]), int(X.shape[1])
+    fn = lib().pdt_project_simplex if str(X.dtype) == "torch.float64" else lib().pdt_project_simplex_f32
+    _check(fn(ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Y.data_ptr()), rows, cols, _stream_ptr(stream)))
+    return Y
+
+
+def pdt_replay_kernel(handle, kernel: int, precision: int, reps: int) -> None:
+    _check(lib().pdt_replay_kernel(handle, int(kernel), int(precision), int(reps)))
+
+
+def pdt_problem_bands(handle, D: int) -> dict:
+    import numpy as np
+    lo = np.zeros(D, dtype=np.int32)
+    hi = np.zeros(D, dtype=np.int32)
+    tail = np.zeros(D, dtype=np.float64)
+    L = ctypes.c_double()
+    nnz = ctypes.c_int64()
+    _check(lib().pdt_problem_bands(handle, lo.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   hi.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   tail.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(L),
+                                   ctypes.byref(nnz)))
+    return {"lo": lo, "hi": hi, "tail": tail, "lipschitz": L.value, "nnz": nnz.value}
+
+
+class Problem:
+    """Owns a problem handle; thin convenience over the pdt_* calls."""
+
+    def __init__(self, mu, P, M, gamma, pmf_threshold, tail_mode, stream=None):
+        self.M = int(M)
+        self.D = int(len(mu))
+        self.N = int(P.shape[1])
+        self.handle = pdt_make_problem(mu, P, M, gamma, pmf_threshold, tail_mode, stream)
+
+    @classmethod
+    def from_instance(cls, inst, stream=None):
+        return cls(inst.mu, inst.P, inst.M, inst.gamma, inst.threshold, inst.tail_mode, stream)
+
+    def solve(self, Pi, **kw):
+        return pdt_solve(self.handle, Pi, **kw)
+
+    def objective(self, Pi, grad=None):
+        return pdt_objective(self.handle, Pi, grad)
+
+    def kkt(self, Pi):
+        return pdt_kkt(self.handle, Pi)
+
+    def bands(self):
+        return pdt_problem_bands(self.handle, self.D)
+
+    def close(self):
+        if self.handle:
+            pdt_destroy_problem(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

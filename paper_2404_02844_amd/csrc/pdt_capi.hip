@@ -1,0 +1,623 @@
+// C ABI and host driver of libpdt: problem setup, the projected-gradient loop, and
+// the objective / projection entry points declared in include/pdt.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pdt.h"
+#include "pdt_internal.h"
+
+using namespace pdt;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct DevError {
+  hipError_t code;
+  std::string what;
+};
+struct OomError {
+  std::string what;
+};
+struct ArgError {
+  std::string what;
+};
+
+#define HIPCHK(...)                                                              \
+  do {                                                                           \
+    hipError_t e_ = (__VA_ARGS__);                                               \
+    if (e_ != hipSuccess)                                                        \
+      throw DevError{e_, std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+// Device allocations owned by one problem.
+struct Arena {
+  std::vector<void*> ptrs;
+  template <typename T>
+  T* alloc(size_t n) {
+    void* p = nullptr;
+    const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw OomError{"hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    }
+    ptrs.push_back(p);
+    return static_cast<T*>(p);
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+template <typename T>
+struct Work {
+  T* X[3] = {nullptr, nullptr, nullptr};
+  T* O[3] = {nullptr, nullptr, nullptr};
+  T* R_acc = nullptr;
+  T* R_rej = nullptr;
+  T* G = nullptr;
+  const T* P = nullptr;
+  bool ready = false;
+};
+
+struct Instance {
+  int64_t M = 0, N = 0, D = 0, Npad = 0;
+  double gamma = 0, tau = 0;
+  int lump = 0;
+  double L_hat = 0;
+  int64_t nnz = 0;
+  std::vector<int> lo_h, hi_h;
+  std::vector<double> tail_h;
+  double* mu = nullptr;
+  int* lo = nullptr;
+  int* hi = nullptr;
+  double* tail = nullptr;
+  double* rinv = nullptr;
+  int* dt_mlo = nullptr;
+  int* dt_mhi = nullptr;
+  int* mt_dlo = nullptr;
+  int* mt_dhi = nullptr;
+  double* P64 = nullptr;
+  float* P32 = nullptr;
+  Work<double> w64;
+  Work<float> w32;
+  double* partials = nullptr;
+  int n_partials = 0;
+  SolverState* st = nullptr;
+  SolverState* st_eval = nullptr;
+  double* scalar = nullptr;
+  SolverState* host_state = nullptr;  // pinned mirror for polling
+};
+
+}  // namespace
+
+struct pdt_problem_s {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  Arena arena;
+  std::vector<Instance> inst;
+};
+
+namespace {
+
+pdt_status set_err(pdt_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+ProbView view_of(const Instance& I) {
+  ProbView pv;
+  pv.mu = I.mu;
+  pv.lo = I.lo;
+  pv.hi = I.hi;
+  pv.tail = I.tail;
+  pv.rinv = I.rinv;
+  pv.dt_mlo = I.dt_mlo;
+  pv.dt_mhi = I.dt_mhi;
+  pv.mt_dlo = I.mt_dlo;
+  pv.mt_dhi = I.mt_dhi;
+  pv.M = (int)I.M;
+  pv.D = (int)I.D;
+  pv.N = (int)I.N;
+  pv.Npad = (int)I.Npad;
+  pv.lump = I.lump;
+  pv.gamma = I.gamma;
+  return pv;
+}
+
+template <typename T>
+Bufs<T> bufs_of(const Instance& I, const Work<T>& w, double* history) {
+  Bufs<T> b;
+  for (int k = 0; k < 3; ++k) {
+    b.X[k] = w.X[k];
+    b.O[k] = w.O[k];
+  }
+  b.P = w.P;
+  b.R_acc = w.R_acc;
+  b.R_rej = w.R_rej;
+  b.G = w.G;
+  b.partials = I.partials;
+  b.n_partials = I.n_partials;
+  b.history = history;
+  return b;
+}
+
+template <typename T>
+void ensure_work(Arena& A, Instance& I, Work<T>& w, const T* P) {
+  if (w.ready) return;
+  const size_t xm = (size_t)I.M * I.Npad, od = (size_t)I.D * I.Npad;
+  for (int k = 0; k < 3; ++k) {
+    w.X[k] = A.alloc<T>(xm);
+    w.O[k] = A.alloc<T>(od);
+  }
+  w.R_acc = A.alloc<T>(od);
+  w.R_rej = A.alloc<T>(od);
+  w.G = A.alloc<T>(xm);
+  w.P = P;
+  w.ready = true;
+}
+
+void validate_desc(const pdt_problem_desc& d) {
+  if (d.M < 1 || d.N < 1 || d.D < 1) throw ArgError{"M, N and D must be >= 1"};
+  if (d.N > 16 * kMaxNT) throw ArgError{"N must be <= " + std::to_string(16 * kMaxNT)};
+  if (d.M > (int64_t)INT_MAX - 1024 || d.D > (int64_t)INT_MAX - 1024) throw ArgError{"M or D too large"};
+  const int64_t npad = (d.N + 15) / 16 * 16;
+  if (d.M > (int64_t)1 << 40 || d.M * npad > ((int64_t)1 << 46)) throw ArgError{"M*N too large"};
+  if (!d.mu || !d.P) throw ArgError{"mu and P must not be NULL"};
+  if (!std::isfinite(d.gamma) || d.gamma < 0) throw ArgError{"gamma must be finite and >= 0"};
+  if (!std::isfinite(d.pmf_threshold) || d.pmf_threshold < 0 || d.pmf_threshold >= 1)
+    throw ArgError{"pmf_threshold must be in [0, 1)"};
+  if (d.tail_mode != PDT_TAIL_TRUNCATE && d.tail_mode != PDT_TAIL_LUMP) throw ArgError{"bad tail_mode"};
+  for (int64_t k = 0; k < d.D; ++k) {
+    const double m = d.mu[k];
+    if (!std::isfinite(m) || m < 0) throw ArgError{"mu must be finite and >= 0"};
+    if (k > 0 && m < d.mu[k - 1]) throw ArgError{"mu must be non-decreasing"};
+    if (m > 1e12) throw ArgError{"mu too large"};
+  }
+  if (!d.P_on_device) {
+    const int64_t n = d.D * d.N;
+    for (int64_t k = 0; k < n; ++k)
+      if (!std::isfinite(d.P[k]) || d.P[k] < 0) throw ArgError{"P must be finite and >= 0"};
+  }
+}
+
+// Power iteration for lambda_max(2 F^T F + 2 gamma L) with the band kernels (N = 1).
+double lipschitz_power(pdt_problem_s* pb, Instance& I, int iters) {
+  Arena tmp;
+  hipStream_t s = pb->stream;
+  ProbView pv = view_of(I);
+  pv.N = 1;
+  pv.Npad = 16;
+  const size_t xm = (size_t)I.M * 16, od = (size_t)I.D * 16;
+  try {
+    Work<double> w;
+    w.X[0] = tmp.alloc<double>(xm);
+    w.X[1] = w.X[2] = w.X[0];
+    w.O[0] = tmp.alloc<double>(od);
+    w.O[1] = w.O[2] = w.O[0];
+    double* Pz = tmp.alloc<double>(od);
+    w.R_rej = tmp.alloc<double>(od);
+    w.R_acc = w.R_rej;
+    w.G = tmp.alloc<double>(xm);
+    w.P = Pz;
+    SolverState* st = tmp.alloc<SolverState>(1);
+    double* lam = tmp.alloc<double>(1);
+    HIPCHK(hipMemsetAsync(Pz, 0, od * sizeof(double), s));
+    std::vector<double> v0(xm, 0.0);
+    const double inv = 1.0 / std::sqrt((double)I.M);
+    for (int64_t m = 0; m < I.M; ++m) v0[(size_t)m * 16] = inv;
+    HIPCHK(hipMemcpyAsync(w.X[0], v0.data(), xm * sizeof(double), hipMemcpyHostToDevice, s));
+    SolverState s0;
+    std::memset(&s0, 0, sizeof(s0));
+    HIPCHK(hipMemcpyAsync(st, &s0, sizeof(s0), hipMemcpyHostToDevice, s));
+    Bufs<double> b = bufs_of(I, w, nullptr);
+    for (int it = 0; it < iters; ++it) {
+      HIPCHK(launch_fx<double>(pv, b, st, FX_EVAL, s));
+      HIPCHK(launch_ftr<double>(pv, b, st, FTR_GRAD, 0.0, s));
+      HIPCHK(launch_power_normalize(w.G, w.X[0], (int)I.M, 16, lam, s));
+    }
+    double lam_h = 0;
+    HIPCHK(hipMemcpyAsync(&lam_h, lam, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    tmp.release();
+    return 1.05 * lam_h;
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    tmp.release();
+    throw;
+  }
+}
+
+void setup_instance(pdt_problem_s* pb, Instance& I, const pdt_problem_desc& d) {
+  Arena& A = pb->arena;
+  hipStream_t s = pb->stream;
+  I.M = d.M;
+  I.N = d.N;
+  I.D = d.D;
+  I.Npad = (d.N + 15) / 16 * 16;
+  I.gamma = d.gamma;
+  I.tau = d.pmf_threshold;
+  I.lump = d.tail_mode == PDT_TAIL_LUMP;
+  const size_t D = (size_t)I.D, M = (size_t)I.M, Np = (size_t)I.Npad, N = (size_t)I.N;
+
+  I.mu = A.alloc<double>(D);
+  I.lo = A.alloc<int>(D);
+  I.hi = A.alloc<int>(D);
+  I.tail = A.alloc<double>(D);
+  I.rinv = A.alloc<double>(M + 128);
+  I.P64 = A.alloc<double>(D * Np);
+  HIPCHK(hipMemcpyAsync(I.mu, d.mu, D * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(I.P64, 0, D * Np * sizeof(double), s));
+  HIPCHK(hipMemcpy2DAsync(I.P64, Np * sizeof(double), d.P, N * sizeof(double), N * sizeof(double), D,
+                          d.P_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+  HIPCHK(launch_fill_rinv(I.rinv, (int)(M + 128), s));
+  HIPCHK(launch_setup_bands(I.mu, (int)D, (int)M, I.tau, I.lump, I.lo, I.hi, I.tail, s));
+
+  I.lo_h.resize(D);
+  I.hi_h.resize(D);
+  I.tail_h.resize(D);
+  HIPCHK(hipMemcpyAsync(I.lo_h.data(), I.lo, D * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(I.hi_h.data(), I.hi, D * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(I.tail_h.data(), I.tail, D * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+
+  // tile work lists: photon-number range of every 16-probe tile, probe range of every
+  // 16-row tile of Pi
+  const size_t n_dt = (D + 15) / 16, n_mt = (M + 15) / 16;
+  std::vector<int> dt_mlo(n_dt, INT_MAX), dt_mhi(n_dt, -1), mt_dlo(n_mt, INT_MAX), mt_dhi(n_mt, -1);
+  I.nnz = 0;
+  for (size_t k = 0; k < D; ++k) {
+    const int l = I.lo_h[k], h = I.hi_h[k];
+    if (l > h) continue;
+    I.nnz += (int64_t)(h - l + 1);
+    const size_t t = k / 16;
+    dt_mlo[t] = std::min(dt_mlo[t], l);
+    dt_mhi[t] = std::max(dt_mhi[t], h);
+    for (int q = l / 16; q <= h / 16; ++q) {
+      mt_dlo[q] = std::min(mt_dlo[q], (int)k);
+      mt_dhi[q] = std::max(mt_dhi[q], (int)k);
+    }
+  }
+  for (size_t t = 0; t < n_dt; ++t)
+    if (dt_mhi[t] < 0) dt_mlo[t] = 0;
+  for (size_t t = 0; t < n_mt; ++t)
+    if (mt_dhi[t] < 0) mt_dlo[t] = 0;
+  I.dt_mlo = A.alloc<int>(n_dt);
+  I.dt_mhi = A.alloc<int>(n_dt);
+  I.mt_dlo = A.alloc<int>(n_mt);
+  I.mt_dhi = A.alloc<int>(n_mt);
+  HIPCHK(hipMemcpyAsync(I.dt_mlo, dt_mlo.data(), n_dt * sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(I.dt_mhi, dt_mhi.data(), n_dt * sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(I.mt_dlo, mt_dlo.data(), n_mt * sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(I.mt_dhi, mt_dhi.data(), n_mt * sizeof(int), hipMemcpyHostToDevice, s));
+
+  I.n_partials = (int)std::max(n_dt, n_mt);
+  I.partials = A.alloc<double>(I.n_partials);
+  I.st = A.alloc<SolverState>(1);
+  I.st_eval = A.alloc<SolverState>(1);
+  I.scalar = A.alloc<double>(4);
+  HIPCHK(hipStreamSynchronize(s));
+  I.L_hat = lipschitz_power(pb, I, 100);
+}
+
+template <typename T>
+Work<T>& work_of(Instance& I);
+template <>
+Work<double>& work_of<double>(Instance& I) { return I.w64; }
+template <>
+Work<float>& work_of<float>(Instance& I) { return I.w32; }
+
+void init_state(hipStream_t s, SolverState* dst, int64_t max_iters, double f_star, double rel_tol) {
+  SolverState s0;
+  std::memset(&s0, 0, sizeof(s0));
+  s0.ix_cur = 0;
+  s0.ix_prev = 0;
+  s0.ix_new = 1;
+  s0.t = 1.0;
+  s0.max_iters = max_iters;
+  s0.f_star = f_star;
+  s0.rel_tol = rel_tol;
+  HIPCHK(hipMemcpyAsync(dst, &s0, sizeof(s0), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+SolverState read_state(hipStream_t s, const SolverState* src) {
+  SolverState h;
+  HIPCHK(hipMemcpyAsync(&h, src, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return h;
+}
+
+// f and (optionally) the gradient of the FP64 iterate already in I.w64.X[0].
+double eval_fp64(pdt_problem_s* pb, Instance& I, bool grad, double* kkt_out) {
+  hipStream_t s = pb->stream;
+  const ProbView pv = view_of(I);
+  Bufs<double> b = bufs_of(I, I.w64, nullptr);
+  init_state(s, I.st_eval, 0, 0.0, 0.0);
+  HIPCHK(launch_fx<double>(pv, b, I.st_eval, FX_EVAL, s));
+  HIPCHK(launch_decide(I.partials, fx_num_waves(pv), I.st_eval, nullptr, DEC_EVAL, s));
+  if (grad || kkt_out) {
+    HIPCHK(launch_ftr<double>(pv, b, I.st_eval, FTR_GRAD, 0.0, s));
+    HIPCHK(launch_reduce_sum(I.partials, ftr_num_waves(pv), I.scalar, s));
+  }
+  SolverState h = read_state(s, I.st_eval);
+  if (kkt_out) {
+    double sum = 0;
+    HIPCHK(hipMemcpyAsync(&sum, I.scalar, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *kkt_out = std::sqrt(sum / ((double)I.M * (double)I.N));
+  }
+  return h.f_eval;
+}
+
+template <typename T>
+void run_loop(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double step, SolverState& out) {
+  hipStream_t s = pb->stream;
+  const ProbView pv = view_of(I);
+  Work<T>& w = work_of<T>(I);
+  Bufs<T> b = bufs_of(I, w, o.history);
+  const int nfx = fx_num_waves(pv);
+  HIPCHK(launch_fx<T>(pv, b, I.st, FX_INIT, s));
+  HIPCHK(launch_decide(I.partials, nfx, I.st, nullptr, DEC_INIT, s));
+  const int64_t chunk = 64;
+  int64_t launched = 0;
+  while (launched < o.max_iters) {
+    const int64_t n = std::min<int64_t>(chunk, o.max_iters - launched);
+    for (int64_t k = 0; k < n; ++k) {
+      HIPCHK(launch_ftr<T>(pv, b, I.st, FTR_STEP, step, s));
+      HIPCHK(launch_fx<T>(pv, b, I.st, FX_ITER, s));
+      HIPCHK(launch_decide(I.partials, nfx, I.st, o.history, DEC_ITER, s));
+    }
+    launched += n;
+    SolverState h = read_state(s, I.st);
+    if (h.done) break;
+  }
+  out = read_state(s, I.st);
+}
+
+}  // namespace
+
+namespace {
+template <typename T>
+void replay_impl(pdt_problem_s* pb, Instance& I, int kernel, int64_t reps) {
+  hipStream_t s = pb->stream;
+  const ProbView pv = view_of(I);
+  Bufs<T> b = bufs_of(I, work_of<T>(I), nullptr);
+  SolverState s0;
+  std::memset(&s0, 0, sizeof(s0));
+  s0.ix_cur = 0;
+  s0.ix_prev = 2;
+  s0.ix_new = 1;
+  s0.t = 3.0;
+  s0.beta = 0.5;
+  s0.sel_acc = 1;
+  s0.f_cur = 1e300;
+  s0.max_iters = LLONG_MAX;
+  HIPCHK(hipMemcpyAsync(I.st_eval, &s0, sizeof(s0), hipMemcpyHostToDevice, s));
+  const double step = 1.0 / I.L_hat;
+  for (int64_t r = 0; r < reps; ++r) {
+    if (kernel == 0 || kernel == 3) HIPCHK(launch_ftr<T>(pv, b, I.st_eval, FTR_STEP, step, s));
+    if (kernel == 1 || kernel == 3) HIPCHK(launch_fx<T>(pv, b, I.st_eval, FX_ITER, s));
+    if (kernel == 2 || kernel == 3)
+      HIPCHK(launch_decide(I.partials, fx_num_waves(pv), I.st_eval, nullptr, DEC_ITER, s));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pdt_last_error(void) { return g_last_error.c_str(); }
+
+pdt_status pdt_make_problem(const pdt_problem_desc* descs, int64_t n_instances, void* stream,
+                            pdt_problem_t* out) {
+  if (!out) return set_err(PDT_ERR_INVALID_ARG, "out must not be NULL");
+  *out = nullptr;
+  if (!descs) return set_err(PDT_ERR_INVALID_ARG, "descs must not be NULL");
+  if (n_instances != 1) return set_err(PDT_ERR_INVALID_ARG, "n_instances must be 1");
+  pdt_problem_s* pb = nullptr;
+  try {
+    for (int64_t k = 0; k < n_instances; ++k) validate_desc(descs[k]);
+    pb = new pdt_problem_s();
+    pb->stream = static_cast<hipStream_t>(stream);
+    HIPCHK(hipGetDevice(&pb->device));
+    pb->inst.resize((size_t)n_instances);
+    for (int64_t k = 0; k < n_instances; ++k) setup_instance(pb, pb->inst[(size_t)k], descs[k]);
+    *out = pb;
+    g_last_error.clear();
+    return PDT_OK;
+  } catch (const ArgError& e) {
+    if (pb) { pb->arena.release(); delete pb; }
+    return set_err(PDT_ERR_INVALID_ARG, e.what);
+  } catch (const OomError& e) {
+    if (pb) { (void)hipStreamSynchronize(pb->stream); pb->arena.release(); delete pb; }
+    return set_err(PDT_ERR_OUT_OF_MEMORY, e.what);
+  } catch (const DevError& e) {
+    if (pb) { (void)hipStreamSynchronize(pb->stream); pb->arena.release(); delete pb; }
+    return set_err(PDT_ERR_DEVICE, e.what);
+  } catch (const std::bad_alloc&) {
+    if (pb) { pb->arena.release(); delete pb; }
+    return set_err(PDT_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
+}
+
+void pdt_destroy_problem(pdt_problem_t problem) {
+  if (!problem) return;
+  (void)hipStreamSynchronize(problem->stream);
+  problem->arena.release();
+  delete problem;
+}
+
+pdt_status pdt_problem_bands(pdt_problem_t pb, int32_t* lo, int32_t* hi, double* tail, double* lipschitz,
+                             int64_t* nnz) {
+  if (!pb) return set_err(PDT_ERR_INVALID_ARG, "problem is NULL");
+  const Instance& I = pb->inst[0];
+  if (lo) std::memcpy(lo, I.lo_h.data(), I.lo_h.size() * sizeof(int32_t));
+  if (hi) std::memcpy(hi, I.hi_h.data(), I.hi_h.size() * sizeof(int32_t));
+  if (tail) std::memcpy(tail, I.tail_h.data(), I.tail_h.size() * sizeof(double));
+  if (lipschitz) *lipschitz = I.L_hat;
+  if (nnz) *nnz = I.nnz;
+  return PDT_OK;
+}
+
+static pdt_status objective_impl(pdt_problem_t pb, const double* Pi, double* f_out, double* grad_out,
+                                 double* kkt_out) {
+  if (!pb || !Pi) return set_err(PDT_ERR_INVALID_ARG, "problem and Pi must not be NULL");
+  try {
+    Instance& I = pb->inst[0];
+    hipStream_t s = pb->stream;
+    ensure_work<double>(pb->arena, I, I.w64, I.P64);
+    const size_t Np = (size_t)I.Npad, N = (size_t)I.N;
+    HIPCHK(hipMemsetAsync(I.w64.X[0], 0, (size_t)I.M * Np * sizeof(double), s));
+    HIPCHK(hipMemcpy2DAsync(I.w64.X[0], Np * sizeof(double), Pi, N * sizeof(double), N * sizeof(double),
+                            (size_t)I.M, hipMemcpyDeviceToDevice, s));
+    const double f = eval_fp64(pb, I, grad_out != nullptr, kkt_out);
+    if (f_out) *f_out = f;
+    if (grad_out) {
+      HIPCHK(hipMemcpy2DAsync(grad_out, N * sizeof(double), I.w64.G, Np * sizeof(double), N * sizeof(double),
+                              (size_t)I.M, hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    return std::isfinite(f) ? PDT_OK : set_err(PDT_ERR_NUMERIC, "objective is not finite");
+  } catch (const OomError& e) {
+    return set_err(PDT_ERR_OUT_OF_MEMORY, e.what);
+  } catch (const DevError& e) {
+    return set_err(PDT_ERR_DEVICE, e.what);
+  }
+}
+
+pdt_status pdt_objective(pdt_problem_t pb, const double* Pi, double* f_out, double* grad_out) {
+  return objective_impl(pb, Pi, f_out, grad_out, nullptr);
+}
+
+pdt_status pdt_kkt(pdt_problem_t pb, const double* Pi, double* kkt_out) {
+  if (!kkt_out) return set_err(PDT_ERR_INVALID_ARG, "kkt_out must not be NULL");
+  return objective_impl(pb, Pi, nullptr, nullptr, kkt_out);
+}
+
+pdt_status pdt_solve(pdt_problem_t pb, double* Pi, const pdt_solve_opts* opts, pdt_solve_info* info) {
+  if (!pb || !Pi || !opts) return set_err(PDT_ERR_INVALID_ARG, "problem, Pi and opts must not be NULL");
+  const pdt_solve_opts o = *opts;
+  if (o.max_iters < 0) return set_err(PDT_ERR_INVALID_ARG, "max_iters must be >= 0");
+  if (!std::isfinite(o.step_L) || o.step_L < 0) return set_err(PDT_ERR_INVALID_ARG, "step_L must be >= 0");
+  if (o.init != PDT_INIT_UNIFORM && o.init != PDT_INIT_USER) return set_err(PDT_ERR_INVALID_ARG, "bad init");
+  if (o.precision != PDT_FP64 && o.precision != PDT_FP32)
+    return set_err(PDT_ERR_INVALID_ARG, "precision not supported");
+  if (!std::isfinite(o.rel_obj_tol) || o.rel_obj_tol < 0 || !std::isfinite(o.f_star))
+    return set_err(PDT_ERR_INVALID_ARG, "bad tolerance");
+  const auto t0 = std::chrono::steady_clock::now();
+  try {
+    Instance& I = pb->inst[0];
+    hipStream_t s = pb->stream;
+    Arena& A = pb->arena;
+    ensure_work<double>(A, I, I.w64, I.P64);
+    const size_t Np = (size_t)I.Npad, N = (size_t)I.N, M = (size_t)I.M;
+    const double L = o.step_L > 0 ? o.step_L : I.L_hat;
+    const double step = 1.0 / L;
+    // starting point in X64[0]: 1/N, or the caller's Pi projected onto the constraints
+    if (o.init == PDT_INIT_USER) {
+      HIPCHK(launch_project_rows<double>(Pi, I.w64.X[0], (long long)M, (int)N, (int)N, (int)Np, s));
+    } else {
+      HIPCHK(launch_fill_rows<double>(I.w64.X[0], (long long)M, (int)N, (int)Np, 1.0 / (double)N, s));
+    }
+    const double f_star = o.f_star > 0 ? o.f_star : 0.0;
+    init_state(s, I.st, o.max_iters, f_star, o.rel_obj_tol);
+    SolverState fin;
+    int ix_final = 0;
+    if (o.precision == PDT_FP64) {
+      run_loop<double>(pb, I, o, step, fin);
+      ix_final = fin.ix_cur;
+      if (ix_final != 0)
+        HIPCHK(hipMemcpyAsync(I.w64.X[0], I.w64.X[ix_final], M * Np * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {
+      if (!I.P32) {
+        I.P32 = A.alloc<float>((size_t)I.D * Np);
+        HIPCHK(launch_convert_pad<double, float>(I.P64, I.P32, (long long)I.D, (int)Np, (int)Np, (int)Np, s));
+      }
+      ensure_work<float>(A, I, I.w32, I.P32);
+      HIPCHK(launch_convert_pad<double, float>(I.w64.X[0], I.w32.X[0], (long long)M, (int)Np, (int)Np, (int)Np, s));
+      run_loop<float>(pb, I, o, step, fin);
+      HIPCHK(launch_convert_pad<float, double>(I.w32.X[fin.ix_cur], I.w64.X[0], (long long)M, (int)Np, (int)Np,
+                                               (int)Np, s));
+    }
+    double kkt = 0;
+    const double f = eval_fp64(pb, I, true, &kkt);
+    HIPCHK(hipMemcpy2DAsync(Pi, N * sizeof(double), I.w64.X[0], Np * sizeof(double), N * sizeof(double), M,
+                            hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const bool conv = f_star > 0 && fin.f_cur - f_star <= o.rel_obj_tol * f_star;
+    if (info) {
+      info->iters = fin.iter;
+      info->rejects = fin.rejects;
+      info->objective = f;
+      info->kkt = kkt;
+      info->L_used = L;
+      info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      info->converged = conv ? 1 : 0;
+    }
+    if (!std::isfinite(f)) return set_err(PDT_ERR_NUMERIC, "objective is not finite");
+    if (f_star > 0 && o.rel_obj_tol > 0 && !conv)
+      return set_err(PDT_ERR_NOT_CONVERGED, "max_iters reached before the tolerance");
+    g_last_error.clear();
+    return PDT_OK;
+  } catch (const OomError& e) {
+    return set_err(PDT_ERR_OUT_OF_MEMORY, e.what);
+  } catch (const DevError& e) {
+    return set_err(PDT_ERR_DEVICE, e.what);
+  }
+}
+
+pdt_status pdt_replay_kernel(pdt_problem_t pb, int kernel, int precision, int64_t reps) {
+  if (!pb || kernel < 0 || kernel > 3 || reps < 0) return set_err(PDT_ERR_INVALID_ARG, "bad arguments");
+  Instance& I = pb->inst[0];
+  try {
+    if (precision == PDT_FP64) {
+      if (!I.w64.ready) return set_err(PDT_ERR_INVALID_ARG, "solve in FP64 once before replaying");
+      replay_impl<double>(pb, I, kernel, reps);
+    } else if (precision == PDT_FP32) {
+      if (!I.w32.ready) return set_err(PDT_ERR_INVALID_ARG, "solve in FP32 once before replaying");
+      replay_impl<float>(pb, I, kernel, reps);
+    } else {
+      return set_err(PDT_ERR_INVALID_ARG, "precision not supported");
+    }
+    return PDT_OK;
+  } catch (const DevError& e) {
+    return set_err(PDT_ERR_DEVICE, e.what);
+  }
+}
+
+pdt_status pdt_project_simplex(const double* X, double* Y, int64_t rows, int64_t cols, void* stream) {
+  if (rows == 0 && cols >= 1 && cols <= 1024) return PDT_OK;
+  if (!X || !Y) return set_err(PDT_ERR_INVALID_ARG, "X and Y must not be NULL");
+  if (rows < 0 || cols < 1 || cols > 1024) return set_err(PDT_ERR_INVALID_ARG, "need rows >= 0, 1 <= cols <= 1024");
+  if (rows > (int64_t)INT_MAX) return set_err(PDT_ERR_INVALID_ARG, "too many rows");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_project_rows<double>(X, Y, (long long)rows, (int)cols, (int)cols, (int)cols, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return set_err(PDT_ERR_DEVICE, hipGetErrorString(e));
+  return PDT_OK;
+}
+
+pdt_status pdt_project_simplex_f32(const float* X, float* Y, int64_t rows, int64_t cols, void* stream) {
+  if (rows == 0 && cols >= 1 && cols <= 1024) return PDT_OK;
+  if (!X || !Y) return set_err(PDT_ERR_INVALID_ARG, "X and Y must not be NULL");
+  if (rows < 0 || cols < 1 || cols > 1024) return set_err(PDT_ERR_INVALID_ARG, "need rows >= 0, 1 <= cols <= 1024");
+  if (rows > (int64_t)INT_MAX) return set_err(PDT_ERR_INVALID_ARG, "too many rows");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_project_rows<float>(X, Y, (long long)rows, (int)cols, (int)cols, (int)cols, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return set_err(PDT_ERR_DEVICE, hipGetErrorString(e));
+  return PDT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Internal declarations shared by the HIP kernels and the host driver of libpdt.
+//
+// Layout in device memory (one tomography instance):
+//   mu      [D]           probe mean photon numbers, FP64
+//   lo, hi  [D]           first/last photon number of each probe's F band (int32)
+//   tail    [D]           F[d][M-1] when the tail is lumped into the last column
+//   rinv    [M + 64]      1/m (rinv[0] = 0), drives the pmf recursion p(m+1) = p(m) mu/(m+1)
+//   dt_mlo/dt_mhi         per 16-probe tile: photon-number range its bands cover
+//   mt_dlo/mt_dhi         per 16-row tile of Pi: probe range whose bands touch it
+//   P       [D][Npad]     outcome frequencies, zero padded to Npad = 16 * ceil(N / 16)
+//   X[3]    [M][Npad]     iterates of Pi (current, previous, candidate; roles rotate)
+//   O[3]    [D][Npad]     F X for the three iterates
+//   R_acc, R_rej [D][Npad] residual F Y - P for the next step, if the candidate is
+//                         accepted / rejected (both formed before the decision)
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pdt {
+
+constexpr int kTile = 16;         // MFMA tile edge
+constexpr int kChunkM = 64;       // photon numbers per forward-product chunk
+constexpr int kChunkD = 64;       // probes per transposed-product chunk
+constexpr int kMaxNT = 12;        // outcome columns up to 192
+constexpr int kWave = 64;
+
+enum FxMode { FX_ITER = 0, FX_INIT = 1, FX_EVAL = 2 };
+enum FtrMode { FTR_STEP = 0, FTR_GRAD = 1 };
+enum DecideMode { DEC_ITER = 0, DEC_INIT = 1, DEC_EVAL = 2 };
+
+// Device-resident solver state of one instance.  Written only by the decide kernel
+// (one thread, vector stores), read by every other kernel.
+struct SolverState {
+  double f_cur;    // objective at the current iterate
+  double f_new;    // objective of the latest candidate
+  double f_eval;   // objective of the last plain evaluation
+  double t;        // momentum parameter t_k
+  double beta;     // extrapolation weight for the next transposed-product launch
+  double f_star;   // target optimum (<= 0: none)
+  double rel_tol;  // stop once f_cur - f_star <= rel_tol * f_star
+  double kkt;      // last KKT residual
+  long long iter;
+  long long rejects;
+  long long max_iters;
+  int ix_cur, ix_prev, ix_new;
+  int sel_acc;     // 1: next step uses R_acc, 0: R_rej
+  int done;
+  int pad_;
+};
+
+struct ProbView {
+  const double* mu;
+  const int* lo;
+  const int* hi;
+  const double* tail;
+  const double* rinv;
+  const int* dt_mlo;
+  const int* dt_mhi;
+  const int* mt_dlo;
+  const int* mt_dhi;
+  int M, D, N, Npad, lump;
+  double gamma;
+};
+
+template <typename T>
+struct Bufs {
+  T* X[3];
+  T* O[3];
+  const T* P;
+  T* R_acc;
+  T* R_rej;
+  T* G;              // gradient output (FTR_GRAD)
+  double* partials;  // one FP64 partial per wave
+  int n_partials;
+  double* history;   // f after every iteration (may be null)
+};
+
+// Launchers (pdt_kernels.hip).
+template <typename T>
+hipError_t launch_fx(const ProbView& pv, const Bufs<T>& b, SolverState* st, int mode, hipStream_t s);
+template <typename T>
+hipError_t launch_ftr(const ProbView& pv, const Bufs<T>& b, SolverState* st, int mode, double step,
+                      hipStream_t s);
+hipError_t launch_decide(const double* partials, int n, SolverState* st, double* history, int mode,
+                         hipStream_t s);
+hipError_t launch_setup_bands(const double* mu, int D, int M, double tau, int lump, int* lo, int* hi,
+                              double* tail, hipStream_t s);
+hipError_t launch_fill_rinv(double* rinv, int n, hipStream_t s);
+template <typename T>
+hipError_t launch_project_rows(const T* X, T* Y, long long rows, int cols, int ld_in, int ld_out,
+                               hipStream_t s);
+hipError_t launch_power_normalize(double* G, double* V, int M, int ld, double* lam_out, hipStream_t s);
+hipError_t launch_reduce_sum(const double* partials, int n, double* out, hipStream_t s);
+template <typename Ts, typename Td>
+hipError_t launch_convert_pad(const Ts* src, Td* dst, long long rows, int cols, int ld_src, int ld_dst,
+                              hipStream_t s);
+
+template <typename T>
+hipError_t launch_fill_rows(T* X, long long rows, int cols, int ld, T value, hipStream_t s);
+
+int fx_num_waves(const ProbView& pv);
+int ftr_num_waves(const ProbView& pv);
+
+}  // namespace pdt

@@ -1,0 +1,755 @@
+// Band-GEMM kernels of the projected-gradient detector-tomography solver (gfx950).
+//
+// The two products of every iteration are banded: F[d][m] is non-negligible only for
+// m in [lo_d, hi_d] (Sec. 3.2, Data distribution), and F is never stored -- each
+// kernel regenerates its F tile in registers from one FP64 anchor per 16 entries and
+// the ratio recursion p(m+1) = p(m) mu / (m+1).
+//
+//   fx_kernel   O = F X over a 16-probe tile (MFMA 16x16x4, A = F tile, B = X rows),
+//               epilogue: ||O - P||^2 partial, residuals for the next step, and the
+//               nearest-neighbour regulariser (Eq. regul) over a slice of rows.
+//   ftr_kernel  G = 2 F^T R + 2 gamma L Y over a 16-row tile of Pi (MFMA, A = F^T tile
+//               staged through LDS, B = R rows); epilogue: gradient step, row-wise
+//               Euclidean projection onto the simplex (Eq. Mp1_proj), write X_{k+1}.
+//   decide      fixed-order FP64 reduction of the per-wave partials, accept/reject and
+//               the momentum scalars.
+//
+// MFMA lane layout (v_mfma_{f64,f32}_16x16x4, measured on gfx950): lane l holds
+// A[l%16][l/16] and B[l/16][l%16]; the result register r of lane l is C[row][l%16] with
+// row = 4*(l/16) + r for FP32 but row = l/16 + 4*r for FP64.  The contraction index
+// k = l/16 is mapped to whichever photon number / probe keeps the lane's F values
+// consecutive.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+
+#include "pdt_internal.h"
+#include "pdt_pmf.h"
+
+namespace pdt {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Acc;
+template <>
+struct Acc<double> {
+  typedef f64x4 type;
+  __device__ static __forceinline__ f64x4 mfma(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // tile row held in result register r of a lane in group kq = lane / 16
+  __device__ static __forceinline__ int row(int kq, int r) { return kq + 4 * r; }
+};
+template <>
+struct Acc<float> {
+  typedef f32x4 type;
+  __device__ static __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ int row(int kq, int r) { return 4 * kq + r; }
+};
+
+template <typename T>
+__device__ __forceinline__ T neg_huge();
+template <>
+__device__ __forceinline__ double neg_huge<double>() { return -DBL_MAX; }
+template <>
+__device__ __forceinline__ float neg_huge<float>() { return -FLT_MAX; }
+
+// ---- reductions inside groups of G consecutive lanes (G = 16 or 64) -------------------
+template <int G, typename V>
+__device__ __forceinline__ V group_sum(V v) {
+#pragma unroll
+  for (int off = G / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, G);
+  return v;
+}
+template <int G, typename V>
+__device__ __forceinline__ V group_max(V v) {
+#pragma unroll
+  for (int off = G / 2; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, G));
+  return v;
+}
+template <int G, typename V>
+__device__ __forceinline__ V group_min(V v) {
+#pragma unroll
+  for (int off = G / 2; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, G));
+  return v;
+}
+template <int G>
+__device__ __forceinline__ int group_isum(int v) {
+#pragma unroll
+  for (int off = G / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, G);
+  return v;
+}
+
+// ---- simplex projection of rows spread over G lanes x V values, R rows per lane -------
+//
+// tau* solves sum_i max(z_i - tau, 0) = 1 and lies in [max z - 1, max z].  A few
+// wavefront-level bisection steps on tau narrow that bracket; then, from the bracket's lower end (a lower
+// bound of tau*), the support-restricted threshold tau <- (sum_{z > tau} z - 1) /
+// #{z > tau} increases monotonically to tau* and stops exactly when the support no
+// longer changes (Michelot 1986).  Entries equal to neg_huge<T>() are padding.
+template <typename T, int G, int V, int R, int BISECT>
+__device__ __forceinline__ void simplex_threshold(const T (&z)[R][V], T (&tau)[R]) {
+  T lo[R], hi[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    T mx = z[r][0];
+#pragma unroll
+    for (int v = 1; v < V; ++v) mx = fmax(mx, z[r][v]);
+    mx = group_max<G>(mx);
+    hi[r] = mx;
+    lo[r] = mx - (T)1;
+  }
+  // Bisection on tau in FP32 arithmetic.  lo moves up only when the FP32 sum is above 1
+  // by more than its rounding error can account for, so lo <= tau* always holds; the
+  // exact phase below needs nothing else from the bracket.
+#pragma unroll 1
+  for (int it = 0; it < BISECT; ++it) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const T mid = lo[r] + (T)0.5 * (hi[r] - lo[r]);
+      float s = 0.0f;
+#pragma unroll
+      for (int v = 0; v < V; ++v) s += (float)fmax(z[r][v] - mid, (T)0);
+      s = group_sum<G>(s);
+      const bool up = s > 1.0f + 1e-4f;
+      lo[r] = up ? mid : lo[r];
+      hi[r] = up ? hi[r] : mid;
+    }
+  }
+  int cnt_prev[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) cnt_prev[r] = -1;
+#pragma unroll 1
+  for (int it = 0; it < 4 * G * V + 8; ++it) {
+    bool settled = true;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      T s = 0;
+      int c = 0;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const bool in = z[r][v] > lo[r];
+        s += in ? z[r][v] : (T)0;
+        c += in ? 1 : 0;
+      }
+      s = group_sum<G>(s);
+      c = group_isum<G>(c);
+      const T t = (s - (T)1) / (T)c;
+      const bool moved = c != cnt_prev[r];
+      cnt_prev[r] = c;
+      // the new threshold never falls below the bracket's lower end
+      lo[r] = moved ? fmax(lo[r], t) : lo[r];
+      tau[r] = t;
+      settled = settled && !moved;
+    }
+    if (__all(settled)) break;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Forward band product O = F X, residuals and objective partials.
+// One wave per 16-probe tile; the wave also sums the regulariser over a slice of rows.
+// ---------------------------------------------------------------------------------------
+template <typename T, int NT>
+__global__ __launch_bounds__(64) void fx_kernel(ProbView pv, Bufs<T> b, SolverState* st, int mode) {
+  if (mode == FX_ITER && st->done) return;
+  typedef typename Acc<T>::type AccT;
+  const int lane = threadIdx.x;
+  const int i = lane & 15;
+  const int kq = lane >> 4;
+  const int w = blockIdx.x;
+  const int W = gridDim.x;
+  const int M = pv.M, D = pv.D, N = pv.N, Npad = pv.Npad;
+
+  const int ix_cur = st->ix_cur;
+  const int ix_x = (mode == FX_ITER) ? st->ix_new : ix_cur;
+  const T* __restrict__ X = b.X[ix_x];
+  T* __restrict__ O = b.O[ix_x];
+  const T* __restrict__ Ocur = b.O[ix_cur];
+
+  double part_data = 0.0;
+  const int n_dt = (D + 15) >> 4;
+  if (w < n_dt) {
+    const int d0 = w << 4;
+    const int d = d0 + i;
+    const bool dval = d < D;
+    const double mu = dval ? pv.mu[d] : 0.0;
+    const int blo = dval ? pv.lo[d] : 1;
+    const int bhi = dval ? pv.hi[d] : 0;
+    const double tl = (dval && pv.lump) ? pv.tail[d] : 0.0;
+    const int lumpm = pv.lump ? M - 1 : -1;
+    const int mlo = pv.dt_mlo[w];
+    const int mhi = pv.dt_mhi[w];
+
+    AccT acc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = AccT{0, 0, 0, 0};
+
+    for (int mb = mlo; mb <= mhi; mb += kChunkM) {
+      const int ms = mb + 16 * kq;
+      double p = 0.0;
+      if (ms <= bhi && ms + 15 >= blo) p = poisson_pmf(ms, mu);
+#pragma unroll 4
+      for (int s = 0; s < 16; ++s) {
+        const int m = ms + s;
+        double f = (m >= blo && m <= bhi) ? p : 0.0;
+        f = (m == lumpm && m >= blo && m <= bhi) ? tl : f;
+        p *= mu * pv.rinv[m + 1];
+        const T a = (T)f;
+        const bool mval = m < M;
+        const T* xr = X + (size_t)(mval ? m : 0) * Npad + i;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const T xv = mval ? xr[nt * 16] : (T)0;
+          acc[nt] = Acc<T>::mfma(a, xv, acc[nt]);
+        }
+      }
+    }
+
+    T beta_acc = 0;
+    if (mode == FX_ITER) {
+      const double t = st->t;
+      const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+      const double tnn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * tn * tn));
+      beta_acc = (T)((tn - 1.0) / tnn);
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int n = nt * 16 + i;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int dd = d0 + Acc<T>::row(kq, r);
+        if (dd < D) {
+          const size_t off = (size_t)dd * Npad + n;
+          const T o = acc[nt][r];
+          const T pv_ = b.P[off];
+          O[off] = o;
+          if (n < N) {
+            const double e = (double)o - (double)pv_;
+            part_data += e * e;
+          }
+          if (mode == FX_ITER) {
+            const T oc = Ocur[off];
+            b.R_acc[off] = o + beta_acc * (o - oc) - pv_;
+            b.R_rej[off] = oc - pv_;
+          } else {
+            b.R_rej[off] = o - pv_;
+          }
+        }
+      }
+    }
+  }
+
+  // regulariser sum_{m in slice} sum_n (X[m][n] - X[m+1][n])^2 over this wave's rows
+  double part_reg = 0.0;
+  if (pv.gamma != 0.0 && M > 1) {
+    const long long pairs = (long long)(M - 1);
+    const long long per = (pairs + W - 1) / W;
+    const long long r0 = (long long)w * per;
+    const long long r1 = r0 + per < pairs ? r0 + per : pairs;
+    for (long long m = r0; m < r1; ++m) {
+      for (int n = lane; n < N; n += 64) {
+        const double e = (double)X[m * Npad + n] - (double)X[(m + 1) * Npad + n];
+        part_reg += e * e;
+      }
+    }
+  }
+  double part = part_data + pv.gamma * part_reg;
+  part = group_sum<64>(part);
+  if (lane == 0) b.partials[w] = part;
+}
+
+// ---------------------------------------------------------------------------------------
+// Transposed band product, regulariser gradient and the projected step.
+// One wave per 16-row tile of Pi.
+// ---------------------------------------------------------------------------------------
+template <typename T, int NT>
+__global__ __launch_bounds__(64) void ftr_kernel(ProbView pv, Bufs<T> b, SolverState* st, int mode,
+                                                 double step) {
+  if (mode == FTR_STEP && st->done) return;
+  typedef typename Acc<T>::type AccT;
+  __shared__ double Ft[kChunkD][17];
+
+  const int lane = threadIdx.x;
+  const int i = lane & 15;
+  const int kq = lane >> 4;
+  const int mt = blockIdx.x;
+  const int m0 = mt << 4;
+  const int M = pv.M, D = pv.D, N = pv.N, Npad = pv.Npad;
+  const int lumpm = pv.lump ? M - 1 : -1;
+  const int dlo = pv.mt_dlo[mt];
+  const int dhi = pv.mt_dhi[mt];
+  const T* __restrict__ R = (mode == FTR_STEP && st->sel_acc) ? b.R_acc : b.R_rej;
+
+  AccT acc[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) acc[nt] = AccT{0, 0, 0, 0};
+
+  for (int dc = dlo; dc <= dhi; dc += kChunkD) {
+    {
+      const int d = dc + lane;
+      double vals[16];
+      bool any = false;
+      double mu = 0.0, tl = 0.0;
+      int blo = 1, bhi = 0;
+      if (d <= dhi) {
+        mu = pv.mu[d];
+        blo = pv.lo[d];
+        bhi = pv.hi[d];
+        tl = pv.lump ? pv.tail[d] : 0.0;
+        any = (m0 <= bhi) && (m0 + 15 >= blo);
+      }
+      double p = any ? poisson_pmf(m0, mu) : 0.0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int m = m0 + j;
+        double f = (m >= blo && m <= bhi) ? p : 0.0;
+        f = (m == lumpm && m >= blo && m <= bhi) ? tl : f;
+        vals[j] = f;
+        p *= mu * pv.rinv[m + 1];
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) Ft[lane][j] = vals[j];
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int s = 0; s < 16; ++s) {
+      const int dd = dc + 16 * kq + s;
+      const T a = (T)Ft[16 * kq + s][i];
+      const bool dval = dd <= dhi;
+      const T* rr = R + (size_t)(dval ? dd : 0) * Npad + i;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const T rv = dval ? rr[nt * 16] : (T)0;
+        acc[nt] = Acc<T>::mfma(a, rv, acc[nt]);
+      }
+    }
+    __syncthreads();
+  }
+
+  const T g2 = (T)(2.0 * pv.gamma);
+  if (mode == FTR_STEP) {
+    const T beta = (T)st->beta;
+    const T* __restrict__ Xc = b.X[st->ix_cur];
+    const T* __restrict__ Xp = b.X[st->ix_prev];
+    T* __restrict__ Xn = b.X[st->ix_new];
+    const T stp = (T)step;
+    T z[4][NT];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + Acc<T>::row(kq, r);
+      const bool mval = m < M;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int n = nt * 16 + i;
+        T zz = (n < N) ? (T)0 : neg_huge<T>();
+        if (mval && n < N) {
+          const size_t off = (size_t)m * Npad + n;
+          const T xc = Xc[off];
+          const T y = xc + beta * (xc - Xp[off]);
+          T ly = 0;
+          if (m > 0) {
+            const T xm = Xc[off - Npad];
+            ly += y - (xm + beta * (xm - Xp[off - Npad]));
+          }
+          if (m < M - 1) {
+            const T xq = Xc[off + Npad];
+            ly += y - (xq + beta * (xq - Xp[off + Npad]));
+          }
+          const T g = (T)2 * acc[nt][r] + g2 * ly;
+          zz = y - stp * g;
+        }
+        z[r][nt] = zz;
+      }
+    }
+    T tau[4];
+    simplex_threshold<T, 16, NT, 4, 8>(z, tau);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + Acc<T>::row(kq, r);
+      if (m < M) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int n = nt * 16 + i;
+          Xn[(size_t)m * Npad + n] = (n < N) ? fmax(z[r][nt] - tau[r], (T)0) : (T)0;
+        }
+      }
+    }
+  } else {
+    // gradient at X_cur (R_rej = F X_cur - P) and the KKT residual partial
+    const T* __restrict__ Xc = b.X[st->ix_cur];
+    double part = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + Acc<T>::row(kq, r);
+      const bool mval = m < M;
+      T g[NT], x[NT];
+      T gmin = FLT_MAX;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int n = nt * 16 + i;
+        g[nt] = 0;
+        x[nt] = 0;
+        if (mval && n < N) {
+          const size_t off = (size_t)m * Npad + n;
+          const T xc = Xc[off];
+          T lx = 0;
+          if (m > 0) lx += xc - Xc[off - Npad];
+          if (m < M - 1) lx += xc - Xc[off + Npad];
+          g[nt] = (T)2 * acc[nt][r] + g2 * lx;
+          x[nt] = xc;
+          gmin = fmin(gmin, g[nt]);
+        }
+        if (mval) b.G[(size_t)m * Npad + n] = g[nt];
+      }
+      gmin = group_min<16>(gmin);
+      if (mval) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int n = nt * 16 + i;
+          if (n < N) {
+            const double e = (double)x[nt] * ((double)g[nt] - (double)gmin);
+            part += e * e;
+          }
+        }
+      }
+    }
+    part = group_sum<64>(part);
+    if (lane == 0) b.partials[mt] = part;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Fixed-order reduction of the partials and the accept/reject decision.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (tid < w) sh[tid] += sh[tid + w];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+__global__ __launch_bounds__(256) void decide_kernel(const double* partials, int n, SolverState* st,
+                                                     double* history, int mode) {
+  __shared__ double sh[256];
+  if (mode == DEC_ITER && st->done) return;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < n; k += 256) s += partials[k];
+  const double f = block_sum256(s, sh);
+  if (threadIdx.x != 0) return;
+  if (mode == DEC_EVAL) {
+    st->f_eval = f;
+    return;
+  }
+  if (mode == DEC_INIT) {
+    st->f_cur = f;
+    st->f_new = f;
+    st->t = 1.0;
+    st->beta = 0.0;
+    st->ix_cur = 0;
+    st->ix_prev = 0;
+    st->ix_new = 1;
+    st->sel_acc = 0;
+    st->iter = 0;
+    st->rejects = 0;
+    st->done = (st->max_iters <= 0) ||
+               (st->f_star > 0.0 && f - st->f_star <= st->rel_tol * st->f_star) ? 1 : 0;
+    return;
+  }
+  const double t = st->t;
+  const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+  double tt;
+  st->f_new = f;
+  if (f <= st->f_cur) {
+    const int c = st->ix_cur, nw = st->ix_new;
+    st->ix_prev = c;
+    st->ix_cur = nw;
+    st->ix_new = 3 - c - nw;
+    st->f_cur = f;
+    st->sel_acc = 1;
+    tt = tn;
+  } else {
+    st->ix_prev = st->ix_cur;
+    st->sel_acc = 0;
+    st->rejects = st->rejects + 1;
+    tt = 1.0;
+  }
+  st->t = tt;
+  st->beta = (tt - 1.0) / (0.5 * (1.0 + sqrt(1.0 + 4.0 * tt * tt)));
+  const long long k = st->iter;
+  if (history) history[k] = st->f_cur;
+  st->iter = k + 1;
+  if (k + 1 >= st->max_iters) st->done = 1;
+  if (st->f_star > 0.0 && st->f_cur - st->f_star <= st->rel_tol * st->f_star) st->done = 1;
+}
+
+__global__ __launch_bounds__(256) void reduce_sum_kernel(const double* partials, int n, double* out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < n; k += 256) s += partials[k];
+  const double f = block_sum256(s, sh);
+  if (threadIdx.x == 0) *out = f;
+}
+
+// ---------------------------------------------------------------------------------------
+// Setup: band edges and lumped tail mass per probe (one thread per probe).
+// ---------------------------------------------------------------------------------------
+__global__ void setup_bands_kernel(const double* mu, int D, int M, double tau, int lump, int* lo,
+                                   int* hi, double* tail) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= D) return;
+  const double m_ = mu[d];
+  const double t = lump ? poisson_upper_tail(m_, M - 1) : 0.0;
+  tail[d] = t;
+  if (tau <= 0.0) {
+    lo[d] = 0;
+    hi[d] = M - 1;
+    return;
+  }
+  const int last = M - 1;
+  auto value = [&](int m) -> double { return (lump && m == last) ? t : poisson_pmf(m, m_); };
+  double fl = floor(m_);
+  int mode = fl > (double)last ? last : (int)fl;
+  if (value(mode) < tau) {
+    // the row never reaches the threshold (tail column excepted)
+    if (lump && t >= tau) {
+      lo[d] = last;
+      hi[d] = last;
+    } else {
+      lo[d] = M;
+      hi[d] = -1;
+    }
+    return;
+  }
+  // first m in [0, mode] with value >= tau (values non-decreasing there)
+  int a = 0, bnd = mode;
+  if (value(0) >= tau) {
+    bnd = 0;
+  } else {
+    while (bnd - a > 1) {
+      const int c = a + (bnd - a) / 2;
+      if (value(c) >= tau) bnd = c; else a = c;
+    }
+  }
+  lo[d] = bnd;
+  // last m in [mode, end] with pmf >= tau (non-increasing there)
+  int end = lump ? last - 1 : last;
+  int h;
+  if (mode >= end) {
+    h = mode;
+  } else if (value(end) >= tau) {
+    h = end;
+  } else {
+    int g = mode, e = end;
+    while (e - g > 1) {
+      const int c = g + (e - g) / 2;
+      if (value(c) >= tau) g = c; else e = c;
+    }
+    h = g;
+  }
+  if (lump && t >= tau) h = last;
+  hi[d] = h;
+}
+
+__global__ void fill_rinv_kernel(double* rinv, int n) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < n) rinv[m] = m == 0 ? 0.0 : 1.0 / (double)m;
+}
+
+// ---------------------------------------------------------------------------------------
+// Row-wise simplex projection of a general [rows][cols] array: one wave per row.
+// ---------------------------------------------------------------------------------------
+template <typename T, int V>
+__global__ __launch_bounds__(64) void project_rows_kernel(const T* X, T* Y, long long rows, int cols,
+                                                          int ld_in, int ld_out) {
+  const long long row = blockIdx.x;
+  if (row >= rows) return;
+  const int lane = threadIdx.x;
+  T z[1][V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const int c = v * 64 + lane;
+    z[0][v] = c < cols ? X[row * ld_in + c] : neg_huge<T>();
+  }
+  T tau[1];
+  simplex_threshold<T, 64, V, 1, 8>(z, tau);
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const int c = v * 64 + lane;
+    if (c < ld_out) Y[row * ld_out + c] = c < cols ? fmax(z[0][v] - tau[0], (T)0) : (T)0;
+  }
+}
+
+// power iteration: lambda = ||G[:,0]||, V[:,0] = G[:,0] / lambda
+__global__ __launch_bounds__(256) void power_normalize_kernel(const double* G, double* V, int M, int ld,
+                                                              double* lam_out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int m = threadIdx.x; m < M; m += 256) {
+    const double g = G[(size_t)m * ld];
+    s += g * g;
+  }
+  const double lam = sqrt(block_sum256(s, sh));
+  const double inv = lam > 0.0 ? 1.0 / lam : 0.0;
+  for (int m = threadIdx.x; m < M; m += 256) V[(size_t)m * ld] = G[(size_t)m * ld] * inv;
+  if (threadIdx.x == 0) *lam_out = lam;
+}
+
+template <typename T>
+__global__ void fill_rows_kernel(T* X, long long rows, int cols, int ld, T value) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * ld) return;
+  const int c = (int)(idx % ld);
+  X[idx] = c < cols ? value : (T)0;
+}
+
+template <typename Ts, typename Td>
+__global__ void convert_pad_kernel(const Ts* src, Td* dst, long long rows, int cols, int ld_src,
+                                   int ld_dst) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = rows * ld_dst;
+  if (idx >= total) return;
+  const long long r = idx / ld_dst;
+  const int c = (int)(idx - r * ld_dst);
+  dst[idx] = c < cols ? (Td)src[r * ld_src + c] : (Td)0;
+}
+
+// ---------------------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------------------
+int fx_num_waves(const ProbView& pv) { return (pv.D + 15) / 16; }
+int ftr_num_waves(const ProbView& pv) { return (pv.M + 15) / 16; }
+
+template <typename T, int NT>
+static void fx_go(const ProbView& pv, const Bufs<T>& b, SolverState* st, int mode, hipStream_t s) {
+  hipLaunchKernelGGL((fx_kernel<T, NT>), dim3(fx_num_waves(pv)), dim3(64), 0, s, pv, b, st, mode);
+}
+template <typename T, int NT>
+static void ftr_go(const ProbView& pv, const Bufs<T>& b, SolverState* st, int mode, double step,
+                   hipStream_t s) {
+  hipLaunchKernelGGL((ftr_kernel<T, NT>), dim3(ftr_num_waves(pv)), dim3(64), 0, s, pv, b, st, mode, step);
+}
+
+#define PDT_NT_SWITCH(NTV, CALL)                 \
+  switch (NTV) {                                 \
+    case 1: CALL(1); break;                      \
+    case 2: CALL(2); break;                      \
+    case 3: CALL(3); break;                      \
+    case 4: CALL(4); break;                      \
+    case 5: CALL(5); break;                      \
+    case 6: CALL(6); break;                      \
+    case 7: CALL(7); break;                      \
+    case 8: CALL(8); break;                      \
+    case 9: CALL(9); break;                      \
+    case 10: CALL(10); break;                    \
+    case 11: CALL(11); break;                    \
+    case 12: CALL(12); break;                    \
+    default: return hipErrorInvalidValue;        \
+  }
+
+template <typename T>
+hipError_t launch_fx(const ProbView& pv, const Bufs<T>& b, SolverState* st, int mode, hipStream_t s) {
+#define PDT_FX(K) fx_go<T, K>(pv, b, st, mode, s)
+  PDT_NT_SWITCH(pv.Npad / 16, PDT_FX)
+#undef PDT_FX
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ftr(const ProbView& pv, const Bufs<T>& b, SolverState* st, int mode, double step,
+                      hipStream_t s) {
+#define PDT_FTR(K) ftr_go<T, K>(pv, b, st, mode, step, s)
+  PDT_NT_SWITCH(pv.Npad / 16, PDT_FTR)
+#undef PDT_FTR
+  return hipGetLastError();
+}
+
+hipError_t launch_decide(const double* partials, int n, SolverState* st, double* history, int mode,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(256), 0, s, partials, n, st, history, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_sum(const double* partials, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(256), 0, s, partials, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_setup_bands(const double* mu, int D, int M, double tau, int lump, int* lo, int* hi,
+                              double* tail, hipStream_t s) {
+  hipLaunchKernelGGL(setup_bands_kernel, dim3((D + 127) / 128), dim3(128), 0, s, mu, D, M, tau, lump, lo,
+                     hi, tail);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_rinv(double* rinv, int n, hipStream_t s) {
+  hipLaunchKernelGGL(fill_rinv_kernel, dim3((n + 255) / 256), dim3(256), 0, s, rinv, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_project_rows(const T* X, T* Y, long long rows, int cols, int ld_in, int ld_out,
+                               hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  const int v = (cols + 63) / 64;
+  const dim3 g((unsigned)rows), blk(64);
+  if (v <= 1) hipLaunchKernelGGL((project_rows_kernel<T, 1>), g, blk, 0, s, X, Y, rows, cols, ld_in, ld_out);
+  else if (v <= 2) hipLaunchKernelGGL((project_rows_kernel<T, 2>), g, blk, 0, s, X, Y, rows, cols, ld_in, ld_out);
+  else if (v <= 4) hipLaunchKernelGGL((project_rows_kernel<T, 4>), g, blk, 0, s, X, Y, rows, cols, ld_in, ld_out);
+  else if (v <= 8) hipLaunchKernelGGL((project_rows_kernel<T, 8>), g, blk, 0, s, X, Y, rows, cols, ld_in, ld_out);
+  else if (v <= 16) hipLaunchKernelGGL((project_rows_kernel<T, 16>), g, blk, 0, s, X, Y, rows, cols, ld_in, ld_out);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_power_normalize(double* G, double* V, int M, int ld, double* lam_out, hipStream_t s) {
+  hipLaunchKernelGGL(power_normalize_kernel, dim3(1), dim3(256), 0, s, G, V, M, ld, lam_out);
+  return hipGetLastError();
+}
+
+template <typename Ts, typename Td>
+hipError_t launch_convert_pad(const Ts* src, Td* dst, long long rows, int cols, int ld_src, int ld_dst,
+                              hipStream_t s) {
+  const long long total = rows * ld_dst;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL((convert_pad_kernel<Ts, Td>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     src, dst, rows, cols, ld_src, ld_dst);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill_rows(T* X, long long rows, int cols, int ld, T value, hipStream_t s) {
+  const long long total = rows * ld;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL((fill_rows_kernel<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, X, rows,
+                     cols, ld, value);
+  return hipGetLastError();
+}
+template hipError_t launch_fill_rows<double>(double*, long long, int, int, double, hipStream_t);
+template hipError_t launch_fill_rows<float>(float*, long long, int, int, float, hipStream_t);
+
+template hipError_t launch_fx<double>(const ProbView&, const Bufs<double>&, SolverState*, int, hipStream_t);
+template hipError_t launch_fx<float>(const ProbView&, const Bufs<float>&, SolverState*, int, hipStream_t);
+template hipError_t launch_ftr<double>(const ProbView&, const Bufs<double>&, SolverState*, int, double,
+                                       hipStream_t);
+template hipError_t launch_ftr<float>(const ProbView&, const Bufs<float>&, SolverState*, int, double,
+                                      hipStream_t);
+template hipError_t launch_project_rows<double>(const double*, double*, long long, int, int, int, hipStream_t);
+template hipError_t launch_project_rows<float>(const float*, float*, long long, int, int, int, hipStream_t);
+template hipError_t launch_convert_pad<double, double>(const double*, double*, long long, int, int, int,
+                                                       hipStream_t);
+template hipError_t launch_convert_pad<double, float>(const double*, float*, long long, int, int, int,
+                                                      hipStream_t);
+template hipError_t launch_convert_pad<float, double>(const float*, double*, long long, int, int, int,
+                                                      hipStream_t);
+
+}  // namespace pdt

@@ -153,17 +153,46 @@ __device__ __forceinline__ void simplex_threshold(const T (&z)[R][V], T (&tau)[R
 
 // ---------------------------------------------------------------------------------------
 // Forward band product O = F X, residuals and objective partials.
-// One wave per 16-probe tile; the wave also sums the regulariser over a slice of rows.
+//
+// One workgroup of KS waves per 16-probe tile; the waves split the tile's photon-number
+// range in 64-wide chunks (wave w takes chunks w, w + KS, ...), each prefetching the X
+// rows of the next PF contraction steps into a register ring.  Partial tiles are summed
+// in LDS in a fixed order, then each wave finishes 4 of the 16 probe rows.  Every
+// workgroup also sums the regulariser over a slice of rows.
 // ---------------------------------------------------------------------------------------
+constexpr int KS = 4;   // waves per workgroup splitting the contraction
+constexpr int PF = 4;   // prefetch depth in contraction steps
+
+// sum the KS partial 16 x (16 NT) tiles of a workgroup into S (LDS, row stride ld)
+template <typename T, int NT, typename AccT>
+__device__ __forceinline__ void reduce_tiles(const AccT (&acc)[NT], double* S, int ld, int wv, int i, int kq) {
+  for (int w = 0; w < KS; ++w) {
+    if (wv == w) {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          double* p = S + Acc<T>::row(kq, r) * ld + nt * 16 + i;
+          *p = (w == 0) ? (double)acc[nt][r] : *p + (double)acc[nt][r];
+        }
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T, int NT>
-__global__ __launch_bounds__(64) void fx_kernel(ProbView pv, Bufs<T> b, SolverState* st, int mode) {
+__global__ __launch_bounds__(64 * KS) void fx_kernel(ProbView pv, Bufs<T> b, SolverState* st, int mode) {
   if (mode == FX_ITER && st->done) return;
   typedef typename Acc<T>::type AccT;
-  const int lane = threadIdx.x;
+  constexpr int LDT = 16 * NT + 1;
+  __shared__ double S[16 * LDT];
+  __shared__ double red[KS];
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6;
+  const int lane = tid & 63;
   const int i = lane & 15;
   const int kq = lane >> 4;
-  const int w = blockIdx.x;
-  const int W = gridDim.x;
+  const int tile = blockIdx.x;
   const int M = pv.M, D = pv.D, N = pv.N, Npad = pv.Npad;
 
   const int ix_cur = st->ix_cur;
@@ -172,115 +201,142 @@ __global__ __launch_bounds__(64) void fx_kernel(ProbView pv, Bufs<T> b, SolverSt
   T* __restrict__ O = b.O[ix_x];
   const T* __restrict__ Ocur = b.O[ix_cur];
 
-  double part_data = 0.0;
-  const int n_dt = (D + 15) >> 4;
-  if (w < n_dt) {
-    const int d0 = w << 4;
-    const int d = d0 + i;
-    const bool dval = d < D;
-    const double mu = dval ? pv.mu[d] : 0.0;
-    const int blo = dval ? pv.lo[d] : 1;
-    const int bhi = dval ? pv.hi[d] : 0;
-    const double tl = (dval && pv.lump) ? pv.tail[d] : 0.0;
-    const int lumpm = pv.lump ? M - 1 : -1;
-    const int mlo = pv.dt_mlo[w];
-    const int mhi = pv.dt_mhi[w];
+  const int d0 = tile << 4;
+  const int d = d0 + i;
+  const bool dval = d < D;
+  const double mu = dval ? pv.mu[d] : 0.0;
+  const int blo = dval ? pv.lo[d] : 1;
+  const int bhi = dval ? pv.hi[d] : 0;
+  const double tl = (dval && pv.lump) ? pv.tail[d] : 0.0;
+  const int lumpm = pv.lump ? M - 1 : -1;
+  const int mlo = pv.dt_mlo[tile];
+  const int mhi = pv.dt_mhi[tile];
 
-    AccT acc[NT];
+  AccT acc[NT];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[nt] = AccT{0, 0, 0, 0};
+  for (int nt = 0; nt < NT; ++nt) acc[nt] = AccT{0, 0, 0, 0};
 
-    for (int mb = mlo; mb <= mhi; mb += kChunkM) {
-      const int ms = mb + 16 * kq;
-      double p = 0.0;
-      if (ms <= bhi && ms + 15 >= blo) p = poisson_pmf(ms, mu);
-#pragma unroll 4
-      for (int s = 0; s < 16; ++s) {
-        const int m = ms + s;
-        double f = (m >= blo && m <= bhi) ? p : 0.0;
-        f = (m == lumpm && m >= blo && m <= bhi) ? tl : f;
-        p *= mu * pv.rinv[m + 1];
-        const T a = (T)f;
-        const bool mval = m < M;
-        const T* xr = X + (size_t)(mval ? m : 0) * Npad + i;
+  // X rows beyond M-1 are clamped: their F entries are zero (outside every band)
+  auto load_x = [&](int mrow, T (&dst)[NT]) {
+    const int m = mrow < M - 1 ? mrow : M - 1;
+    const T* xr = X + (size_t)m * Npad + i;
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const T xv = mval ? xr[nt * 16] : (T)0;
-          acc[nt] = Acc<T>::mfma(a, xv, acc[nt]);
-        }
-      }
+    for (int nt = 0; nt < NT; ++nt) dst[nt] = xr[nt * 16];
+  };
+  constexpr int stride = kChunkM * KS;
+  int mb = mlo + kChunkM * wv;
+  T xb[PF][NT];
+  if (mb <= mhi) {
+#pragma unroll
+    for (int p = 0; p < PF; ++p) load_x(mb + 16 * kq + p, xb[p]);
+  }
+  for (; mb <= mhi; mb += stride) {
+    const int mbn = mb + stride;
+    const bool more = mbn <= mhi;
+    const int ms = mb + 16 * kq;
+    double p = 0.0;
+    if (ms <= bhi && ms + 15 >= blo) p = poisson_pmf(ms, mu);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int m = ms + s;
+      double f = (m >= blo && m <= bhi) ? p : 0.0;
+      f = (m == lumpm && m >= blo && m <= bhi) ? tl : f;
+      p *= mu / (double)(m + 1);
+      const T a = (T)f;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[nt] = Acc<T>::mfma(a, xb[s % PF][nt], acc[nt]);
+      if (s + PF < 16) load_x(ms + s + PF, xb[s % PF]);
+      else if (more) load_x(mbn + 16 * kq + s + PF - 16, xb[s % PF]);
     }
+  }
+  reduce_tiles<T, NT>(acc, S, LDT, wv, i, kq);
 
-    T beta_acc = 0;
-    if (mode == FX_ITER) {
-      const double t = st->t;
-      const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
-      const double tnn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * tn * tn));
-      beta_acc = (T)((tn - 1.0) / tnn);
-    }
+  // epilogue: wave wv finishes probe rows 4 wv + kq
+  T beta_acc = 0;
+  if (mode == FX_ITER) {
+    const double t = st->t;
+    const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+    const double tnn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * tn * tn));
+    beta_acc = (T)((tn - 1.0) / tnn);
+  }
+  double part = 0.0;
+  const int dd = d0 + 4 * wv + kq;
+  if (dd < D) {
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const int n = nt * 16 + i;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int dd = d0 + Acc<T>::row(kq, r);
-        if (dd < D) {
-          const size_t off = (size_t)dd * Npad + n;
-          const T o = acc[nt][r];
-          const T pv_ = b.P[off];
-          O[off] = o;
-          if (n < N) {
-            const double e = (double)o - (double)pv_;
-            part_data += e * e;
-          }
-          if (mode == FX_ITER) {
-            const T oc = Ocur[off];
-            b.R_acc[off] = o + beta_acc * (o - oc) - pv_;
-            b.R_rej[off] = oc - pv_;
-          } else {
-            b.R_rej[off] = o - pv_;
-          }
-        }
+      const size_t off = (size_t)dd * Npad + n;
+      const T o = (T)S[(4 * wv + kq) * LDT + n];
+      const T pv_ = b.P[off];
+      O[off] = o;
+      if (n < N) {
+        const double e = (double)o - (double)pv_;
+        part += e * e;
+      }
+      if (mode == FX_ITER) {
+        const T oc = Ocur[off];
+        b.R_acc[off] = o + beta_acc * (o - oc) - pv_;
+        b.R_rej[off] = oc - pv_;
+      } else {
+        b.R_rej[off] = o - pv_;
       }
     }
   }
 
-  // regulariser sum_{m in slice} sum_n (X[m][n] - X[m+1][n])^2 over this wave's rows
-  double part_reg = 0.0;
+  // regulariser over this workgroup's slice of row pairs
   if (pv.gamma != 0.0 && M > 1) {
+    double reg = 0.0;
     const long long pairs = (long long)(M - 1);
+    const long long W = gridDim.x;
     const long long per = (pairs + W - 1) / W;
-    const long long r0 = (long long)w * per;
+    const long long r0 = (long long)tile * per;
     const long long r1 = r0 + per < pairs ? r0 + per : pairs;
-    for (long long m = r0; m < r1; ++m) {
-      for (int n = lane; n < N; n += 64) {
-        const double e = (double)X[m * Npad + n] - (double)X[(m + 1) * Npad + n];
-        part_reg += e * e;
-      }
+    const long long cnt = (r1 > r0 ? r1 - r0 : 0) * (long long)N;
+    for (long long q = tid; q < cnt; q += 64 * KS) {
+      const long long m = r0 + q / N;
+      const int n = (int)(q % N);
+      const double e = (double)X[m * Npad + n] - (double)X[(m + 1) * Npad + n];
+      reg += e * e;
     }
+    part += pv.gamma * reg;
   }
-  double part = part_data + pv.gamma * part_reg;
   part = group_sum<64>(part);
-  if (lane == 0) b.partials[w] = part;
+  if (lane == 0) red[wv] = part;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < KS; ++w) s += red[w];
+    b.partials[tile] = s;
+  }
 }
 
 // ---------------------------------------------------------------------------------------
 // Transposed band product, regulariser gradient and the projected step.
-// One wave per 16-row tile of Pi.
+//
+// One workgroup of KS waves per 16-row tile of Pi; the waves split the tile's probe
+// range in 64-probe chunks.  Per chunk a wave generates F[d][m0..m0+15] for its 64
+// probes (lane = probe, recursion along m) into its own LDS slice and reads it back
+// transposed as the MFMA A operand; the R rows of the next PF steps are prefetched.
 // ---------------------------------------------------------------------------------------
 template <typename T, int NT>
-__global__ __launch_bounds__(64) void ftr_kernel(ProbView pv, Bufs<T> b, SolverState* st, int mode,
-                                                 double step) {
+__global__ __launch_bounds__(64 * KS) void ftr_kernel(ProbView pv, Bufs<T> b, SolverState* st, int mode,
+                                                       double step) {
   if (mode == FTR_STEP && st->done) return;
   typedef typename Acc<T>::type AccT;
-  __shared__ double Ft[kChunkD][17];
+  constexpr int LDT = 16 * NT + 1;
+  __shared__ double Ft[KS][kChunkD][17];
+  __shared__ double S[16 * LDT];
+  __shared__ double red[KS];
 
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6;
+  const int lane = tid & 63;
   const int i = lane & 15;
   const int kq = lane >> 4;
   const int mt = blockIdx.x;
   const int m0 = mt << 4;
-  const int M = pv.M, D = pv.D, N = pv.N, Npad = pv.Npad;
+  const int M = pv.M, N = pv.N, Npad = pv.Npad;
   const int lumpm = pv.lump ? M - 1 : -1;
   const int dlo = pv.mt_dlo[mt];
   const int dhi = pv.mt_dhi[mt];
@@ -290,13 +346,27 @@ __global__ __launch_bounds__(64) void ftr_kernel(ProbView pv, Bufs<T> b, SolverS
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) acc[nt] = AccT{0, 0, 0, 0};
 
-  for (int dc = dlo; dc <= dhi; dc += kChunkD) {
+  // probes beyond dhi are clamped: their generated F entries are zero
+  auto load_r = [&](int drow, T (&dst)[NT]) {
+    const int dd = drow < dhi ? drow : dhi;
+    const T* rr = R + (size_t)(dd > 0 ? dd : 0) * Npad + i;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) dst[nt] = rr[nt * 16];
+  };
+  const int nchunks = dhi >= dlo ? (dhi - dlo) / kChunkD + 1 : 0;
+  const int rounds = (nchunks + KS - 1) / KS;
+  constexpr int stride = kChunkD * KS;
+  int dc = dlo + kChunkD * wv;
+  T rb[PF][NT];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) load_r(dc + 16 * kq + p, rb[p]);
+  for (int rd = 0; rd < rounds; ++rd, dc += stride) {
+    const int dcn = dc + stride;
     {
       const int d = dc + lane;
-      double vals[16];
-      bool any = false;
       double mu = 0.0, tl = 0.0;
       int blo = 1, bhi = 0;
+      bool any = false;
       if (d <= dhi) {
         mu = pv.mu[d];
         blo = pv.lo[d];
@@ -310,28 +380,26 @@ __global__ __launch_bounds__(64) void ftr_kernel(ProbView pv, Bufs<T> b, SolverS
         const int m = m0 + j;
         double f = (m >= blo && m <= bhi) ? p : 0.0;
         f = (m == lumpm && m >= blo && m <= bhi) ? tl : f;
-        vals[j] = f;
-        p *= mu * pv.rinv[m + 1];
+        Ft[wv][lane][j] = f;
+        p *= mu / (double)(m + 1);
       }
-#pragma unroll
-      for (int j = 0; j < 16; ++j) Ft[lane][j] = vals[j];
     }
     __syncthreads();
-#pragma unroll 4
-    for (int s = 0; s < 16; ++s) {
-      const int dd = dc + 16 * kq + s;
-      const T a = (T)Ft[16 * kq + s][i];
-      const bool dval = dd <= dhi;
-      const T* rr = R + (size_t)(dval ? dd : 0) * Npad + i;
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const T rv = dval ? rr[nt * 16] : (T)0;
-        acc[nt] = Acc<T>::mfma(a, rv, acc[nt]);
-      }
+    for (int s = 0; s < 16; ++s) {
+      const T a = (T)Ft[wv][16 * kq + s][i];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[nt] = Acc<T>::mfma(a, rb[s % PF][nt], acc[nt]);
+      if (s + PF < 16) load_r(dc + 16 * kq + s + PF, rb[s % PF]);
+      else load_r(dcn + 16 * kq + s + PF - 16, rb[s % PF]);
     }
     __syncthreads();
   }
+  reduce_tiles<T, NT>(acc, S, LDT, wv, i, kq);
 
+  // epilogue: wave wv finishes rows m0 + 4 wv + kq (one row per 16-lane group)
+  const int m = m0 + 4 * wv + kq;
+  const bool mval = m < M;
   const T g2 = (T)(2.0 * pv.gamma);
   if (mode == FTR_STEP) {
     const T beta = (T)st->beta;
@@ -339,88 +407,81 @@ __global__ __launch_bounds__(64) void ftr_kernel(ProbView pv, Bufs<T> b, SolverS
     const T* __restrict__ Xp = b.X[st->ix_prev];
     T* __restrict__ Xn = b.X[st->ix_new];
     const T stp = (T)step;
-    T z[4][NT];
+    T z[1][NT];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = m0 + Acc<T>::row(kq, r);
-      const bool mval = m < M;
+    for (int nt = 0; nt < NT; ++nt) {
+      const int n = nt * 16 + i;
+      T zz = (n < N) ? (T)0 : neg_huge<T>();
+      if (mval && n < N) {
+        const size_t off = (size_t)m * Npad + n;
+        const T xc = Xc[off];
+        const T y = xc + beta * (xc - Xp[off]);
+        T ly = 0;
+        if (m > 0) {
+          const T xm = Xc[off - Npad];
+          ly += y - (xm + beta * (xm - Xp[off - Npad]));
+        }
+        if (m < M - 1) {
+          const T xq = Xc[off + Npad];
+          ly += y - (xq + beta * (xq - Xp[off + Npad]));
+        }
+        const T g = (T)2 * (T)S[(4 * wv + kq) * LDT + n] + g2 * ly;
+        zz = y - stp * g;
+      }
+      z[0][nt] = zz;
+    }
+    T tau[1];
+    simplex_threshold<T, 16, NT, 1, 8>(z, tau);
+    if (mval) {
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         const int n = nt * 16 + i;
-        T zz = (n < N) ? (T)0 : neg_huge<T>();
-        if (mval && n < N) {
-          const size_t off = (size_t)m * Npad + n;
-          const T xc = Xc[off];
-          const T y = xc + beta * (xc - Xp[off]);
-          T ly = 0;
-          if (m > 0) {
-            const T xm = Xc[off - Npad];
-            ly += y - (xm + beta * (xm - Xp[off - Npad]));
-          }
-          if (m < M - 1) {
-            const T xq = Xc[off + Npad];
-            ly += y - (xq + beta * (xq - Xp[off + Npad]));
-          }
-          const T g = (T)2 * acc[nt][r] + g2 * ly;
-          zz = y - stp * g;
-        }
-        z[r][nt] = zz;
-      }
-    }
-    T tau[4];
-    simplex_threshold<T, 16, NT, 4, 8>(z, tau);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = m0 + Acc<T>::row(kq, r);
-      if (m < M) {
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const int n = nt * 16 + i;
-          Xn[(size_t)m * Npad + n] = (n < N) ? fmax(z[r][nt] - tau[r], (T)0) : (T)0;
-        }
+        Xn[(size_t)m * Npad + n] = (n < N) ? fmax(z[0][nt] - tau[0], (T)0) : (T)0;
       }
     }
   } else {
     // gradient at X_cur (R_rej = F X_cur - P) and the KKT residual partial
     const T* __restrict__ Xc = b.X[st->ix_cur];
     double part = 0.0;
+    T g[NT], x[NT];
+    T gmin = FLT_MAX;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = m0 + Acc<T>::row(kq, r);
-      const bool mval = m < M;
-      T g[NT], x[NT];
-      T gmin = FLT_MAX;
+    for (int nt = 0; nt < NT; ++nt) {
+      const int n = nt * 16 + i;
+      g[nt] = 0;
+      x[nt] = 0;
+      if (mval && n < N) {
+        const size_t off = (size_t)m * Npad + n;
+        const T xc = Xc[off];
+        T lx = 0;
+        if (m > 0) lx += xc - Xc[off - Npad];
+        if (m < M - 1) lx += xc - Xc[off + Npad];
+        g[nt] = (T)2 * (T)S[(4 * wv + kq) * LDT + n] + g2 * lx;
+        x[nt] = xc;
+        gmin = fmin(gmin, g[nt]);
+      }
+      if (mval) b.G[(size_t)m * Npad + n] = g[nt];
+    }
+    gmin = group_min<16>(gmin);
+    if (mval) {
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         const int n = nt * 16 + i;
-        g[nt] = 0;
-        x[nt] = 0;
-        if (mval && n < N) {
-          const size_t off = (size_t)m * Npad + n;
-          const T xc = Xc[off];
-          T lx = 0;
-          if (m > 0) lx += xc - Xc[off - Npad];
-          if (m < M - 1) lx += xc - Xc[off + Npad];
-          g[nt] = (T)2 * acc[nt][r] + g2 * lx;
-          x[nt] = xc;
-          gmin = fmin(gmin, g[nt]);
-        }
-        if (mval) b.G[(size_t)m * Npad + n] = g[nt];
-      }
-      gmin = group_min<16>(gmin);
-      if (mval) {
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const int n = nt * 16 + i;
-          if (n < N) {
-            const double e = (double)x[nt] * ((double)g[nt] - (double)gmin);
-            part += e * e;
-          }
+        if (n < N) {
+          const double e = (double)x[nt] * ((double)g[nt] - (double)gmin);
+          part += e * e;
         }
       }
     }
     part = group_sum<64>(part);
-    if (lane == 0) b.partials[mt] = part;
+    if (lane == 0) red[wv] = part;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < KS; ++w) s += red[w];
+      b.partials[mt] = s;
+    }
   }
 }
 
@@ -631,12 +692,12 @@ int ftr_num_waves(const ProbView& pv) { return (pv.M + 15) / 16; }
 
 template <typename T, int NT>
 static void fx_go(const ProbView& pv, const Bufs<T>& b, SolverState* st, int mode, hipStream_t s) {
-  hipLaunchKernelGGL((fx_kernel<T, NT>), dim3(fx_num_waves(pv)), dim3(64), 0, s, pv, b, st, mode);
+  hipLaunchKernelGGL((fx_kernel<T, NT>), dim3(fx_num_waves(pv)), dim3(64 * KS), 0, s, pv, b, st, mode);
 }
 template <typename T, int NT>
 static void ftr_go(const ProbView& pv, const Bufs<T>& b, SolverState* st, int mode, double step,
                    hipStream_t s) {
-  hipLaunchKernelGGL((ftr_kernel<T, NT>), dim3(ftr_num_waves(pv)), dim3(64), 0, s, pv, b, st, mode, step);
+  hipLaunchKernelGGL((ftr_kernel<T, NT>), dim3(ftr_num_waves(pv)), dim3(64 * KS), 0, s, pv, b, st, mode, step);
 }
 
 #define PDT_NT_SWITCH(NTV, CALL)                 \

@@ -83,6 +83,9 @@ struct Instance {
   int* hi = nullptr;
   double* tail = nullptr;
   double* rinv = nullptr;
+  double* r4 = nullptr;
+  double* anchors = nullptr;
+  long long* mt_aoff = nullptr;
   int* dt_mlo = nullptr;
   int* dt_mhi = nullptr;
   int* mt_dlo = nullptr;
@@ -96,13 +99,18 @@ struct Instance {
   SolverState* st = nullptr;
   SolverState* st_eval = nullptr;
   double* scalar = nullptr;
-  SolverState* host_state = nullptr;  // pinned mirror for polling
+  // captured chunk of iterations, reused while (precision, step, history) match
+  hipGraphExec_t graph = nullptr;
+  int graph_prec = -1;
+  double graph_step = 0.0;
+  double* graph_hist = nullptr;
 };
 
 }  // namespace
 
 struct pdt_problem_s {
   hipStream_t stream = nullptr;
+  hipStream_t capture = nullptr;  // library-owned stream used only to record graphs
   int device = 0;
   Arena arena;
   std::vector<Instance> inst;
@@ -122,6 +130,9 @@ ProbView view_of(const Instance& I) {
   pv.hi = I.hi;
   pv.tail = I.tail;
   pv.rinv = I.rinv;
+  pv.r4 = I.r4;
+  pv.anchors = I.anchors;
+  pv.mt_aoff = I.mt_aoff;
   pv.dt_mlo = I.dt_mlo;
   pv.dt_mhi = I.dt_mhi;
   pv.mt_dlo = I.mt_dlo;
@@ -255,12 +266,13 @@ void setup_instance(pdt_problem_s* pb, Instance& I, const pdt_problem_desc& d) {
   I.hi = A.alloc<int>(D);
   I.tail = A.alloc<double>(D);
   I.rinv = A.alloc<double>(M + 128);
+  I.r4 = A.alloc<double>(M + 128);
   I.P64 = A.alloc<double>(D * Np);
   HIPCHK(hipMemcpyAsync(I.mu, d.mu, D * sizeof(double), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemsetAsync(I.P64, 0, D * Np * sizeof(double), s));
   HIPCHK(hipMemcpy2DAsync(I.P64, Np * sizeof(double), d.P, N * sizeof(double), N * sizeof(double), D,
                           d.P_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
-  HIPCHK(launch_fill_rinv(I.rinv, (int)(M + 128), s));
+  HIPCHK(launch_fill_rinv(I.rinv, I.r4, (int)(M + 128), s));
   HIPCHK(launch_setup_bands(I.mu, (int)D, (int)M, I.tau, I.lump, I.lo, I.hi, I.tail, s));
 
   I.lo_h.resize(D);
@@ -300,6 +312,14 @@ void setup_instance(pdt_problem_s* pb, Instance& I, const pdt_problem_desc& d) {
   HIPCHK(hipMemcpyAsync(I.dt_mhi, dt_mhi.data(), n_dt * sizeof(int), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(I.mt_dlo, mt_dlo.data(), n_mt * sizeof(int), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(I.mt_dhi, mt_dhi.data(), n_mt * sizeof(int), hipMemcpyHostToDevice, s));
+
+  // anchors of the transposed product: one FP64 value per (row tile, probe in its range)
+  std::vector<long long> aoff(n_mt + 1, 0);
+  for (size_t t = 0; t < n_mt; ++t) aoff[t + 1] = aoff[t] + (mt_dhi[t] >= mt_dlo[t] ? mt_dhi[t] - mt_dlo[t] + 1 : 0);
+  I.mt_aoff = A.alloc<long long>(n_mt + 1);
+  I.anchors = A.alloc<double>((size_t)aoff[n_mt]);
+  HIPCHK(hipMemcpyAsync(I.mt_aoff, aoff.data(), (n_mt + 1) * sizeof(long long), hipMemcpyHostToDevice, s));
+  HIPCHK(launch_setup_anchors(view_of(I), I.mt_aoff, I.anchors, s));
 
   I.n_partials = (int)std::max(n_dt, n_mt);
   I.partials = A.alloc<double>(I.n_partials);
@@ -360,25 +380,71 @@ double eval_fp64(pdt_problem_s* pb, Instance& I, bool grad, double* kkt_out) {
   return h.f_eval;
 }
 
+constexpr int64_t kGraphIters = 64;
+
 template <typename T>
-void run_loop(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double step, SolverState& out) {
+void enqueue_iters(const ProbView& pv, const Bufs<T>& b, SolverState* st, double step, int64_t n, hipStream_t s) {
+  const int nfx = fx_num_waves(pv);
+  for (int64_t k = 0; k < n; ++k) {
+    HIPCHK(launch_ftr<T>(pv, b, st, FTR_STEP, step, s));
+    HIPCHK(launch_fx<T>(pv, b, st, FX_ITER, s));
+    HIPCHK(launch_decide(b.partials, nfx, st, b.history, DEC_ITER, s));
+  }
+}
+
+void drop_graph(Instance& I) {
+  if (I.graph) (void)hipGraphExecDestroy(I.graph);
+  I.graph = nullptr;
+  I.graph_prec = -1;
+}
+
+// Iterations are launched kGraphIters at a time from one captured graph; kernels read
+// the device state and return at once after it says done, so surplus launches of the
+// last chunk cost only their launch.
+template <typename T>
+void run_loop(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double step, int prec, SolverState& out) {
   hipStream_t s = pb->stream;
   const ProbView pv = view_of(I);
   Work<T>& w = work_of<T>(I);
   Bufs<T> b = bufs_of(I, w, o.history);
-  const int nfx = fx_num_waves(pv);
   HIPCHK(launch_fx<T>(pv, b, I.st, FX_INIT, s));
-  HIPCHK(launch_decide(I.partials, nfx, I.st, nullptr, DEC_INIT, s));
-  const int64_t chunk = 64;
+  HIPCHK(launch_decide(I.partials, fx_num_waves(pv), I.st, nullptr, DEC_INIT, s));
+  const bool use_graph = o.max_iters >= kGraphIters;
+  if (use_graph && !(I.graph && I.graph_prec == prec && I.graph_step == step && I.graph_hist == o.history)) {
+    drop_graph(I);
+    // recorded on the library's own stream (the caller's may be the legacy default
+    // stream, which cannot be captured); replayed on the caller's stream
+    if (!pb->capture) HIPCHK(hipStreamCreateWithFlags(&pb->capture, hipStreamNonBlocking));
+    hipStream_t cs = pb->capture;
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    try {
+      enqueue_iters<T>(pv, b, I.st, step, kGraphIters, cs);
+    } catch (...) {
+      (void)hipStreamEndCapture(cs, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIPCHK(hipStreamEndCapture(cs, &g));
+    hipGraphExec_t ge = nullptr;
+    hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(e);
+    I.graph = ge;
+    I.graph_prec = prec;
+    I.graph_step = step;
+    I.graph_hist = o.history;
+  }
   int64_t launched = 0;
   while (launched < o.max_iters) {
-    const int64_t n = std::min<int64_t>(chunk, o.max_iters - launched);
-    for (int64_t k = 0; k < n; ++k) {
-      HIPCHK(launch_ftr<T>(pv, b, I.st, FTR_STEP, step, s));
-      HIPCHK(launch_fx<T>(pv, b, I.st, FX_ITER, s));
-      HIPCHK(launch_decide(I.partials, nfx, I.st, o.history, DEC_ITER, s));
+    if (use_graph) {
+      HIPCHK(hipGraphLaunch(I.graph, s));
+      launched += kGraphIters;
+    } else {
+      const int64_t n = o.max_iters - launched;
+      enqueue_iters<T>(pv, b, I.st, step, n, s);
+      launched += n;
     }
-    launched += n;
     SolverState h = read_state(s, I.st);
     if (h.done) break;
   }
@@ -454,6 +520,8 @@ pdt_status pdt_make_problem(const pdt_problem_desc* descs, int64_t n_instances, 
 void pdt_destroy_problem(pdt_problem_t problem) {
   if (!problem) return;
   (void)hipStreamSynchronize(problem->stream);
+  for (Instance& I : problem->inst) drop_graph(I);
+  if (problem->capture) (void)hipStreamDestroy(problem->capture);
   problem->arena.release();
   delete problem;
 }
@@ -535,7 +603,7 @@ pdt_status pdt_solve(pdt_problem_t pb, double* Pi, const pdt_solve_opts* opts, p
     SolverState fin;
     int ix_final = 0;
     if (o.precision == PDT_FP64) {
-      run_loop<double>(pb, I, o, step, fin);
+      run_loop<double>(pb, I, o, step, PDT_FP64, fin);
       ix_final = fin.ix_cur;
       if (ix_final != 0)
         HIPCHK(hipMemcpyAsync(I.w64.X[0], I.w64.X[ix_final], M * Np * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -546,7 +614,7 @@ pdt_status pdt_solve(pdt_problem_t pb, double* Pi, const pdt_solve_opts* opts, p
       }
       ensure_work<float>(A, I, I.w32, I.P32);
       HIPCHK(launch_convert_pad<double, float>(I.w64.X[0], I.w32.X[0], (long long)M, (int)Np, (int)Np, (int)Np, s));
-      run_loop<float>(pb, I, o, step, fin);
+      run_loop<float>(pb, I, o, step, PDT_FP32, fin);
       HIPCHK(launch_convert_pad<float, double>(I.w32.X[fin.ix_cur], I.w64.X[0], (long long)M, (int)Np, (int)Np,
                                                (int)Np, s));
     }

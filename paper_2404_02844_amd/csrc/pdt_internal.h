@@ -4,7 +4,9 @@
 //   mu      [D]           probe mean photon numbers, FP64
 //   lo, hi  [D]           first/last photon number of each probe's F band (int32)
 //   tail    [D]           F[d][M-1] when the tail is lumped into the last column
-//   rinv    [M + 64]      1/m (rinv[0] = 0), drives the pmf recursion p(m+1) = p(m) mu/(m+1)
+//   rinv    [M + 128]     1/m (rinv[0] = 0): the recursion p(m+1) = p(m) mu / (m+1)
+//   r4      [M + 128]     1/((m+1)(m+2)(m+3)(m+4)): the stride-4 recursion of the forward product
+//   anchors               F[d][16 t] for each 16-row tile t and each probe d it meets
 //   dt_mlo/dt_mhi         per 16-probe tile: photon-number range its bands cover
 //   mt_dlo/mt_dhi         per 16-row tile of Pi: probe range whose bands touch it
 //   P       [D][Npad]     outcome frequencies, zero padded to Npad = 16 * ceil(N / 16)
@@ -56,6 +58,9 @@ struct ProbView {
   const int* hi;
   const double* tail;
   const double* rinv;
+  const double* r4;       // 1 / ((m+1)(m+2)(m+3)(m+4))
+  const double* anchors;  // F[d][16 t] per row tile t and probe d of its range
+  const long long* mt_aoff;
   const int* dt_mlo;
   const int* dt_mhi;
   const int* mt_dlo;
@@ -87,7 +92,8 @@ hipError_t launch_decide(const double* partials, int n, SolverState* st, double*
                          hipStream_t s);
 hipError_t launch_setup_bands(const double* mu, int D, int M, double tau, int lump, int* lo, int* hi,
                               double* tail, hipStream_t s);
-hipError_t launch_fill_rinv(double* rinv, int n, hipStream_t s);
+hipError_t launch_fill_rinv(double* rinv, double* r4, int n, hipStream_t s);
+hipError_t launch_setup_anchors(const ProbView& pv, const long long* mt_aoff, double* anchors, hipStream_t s);
 template <typename T>
 hipError_t launch_project_rows(const T* X, T* Y, long long rows, int cols, int ld_in, int ld_out,
                                hipStream_t s);

@@ -216,37 +216,45 @@ __global__ __launch_bounds__(64 * KS) void fx_kernel(ProbView pv, Bufs<T> b, Sol
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) acc[nt] = AccT{0, 0, 0, 0};
 
-  // X rows beyond M-1 are clamped: their F entries are zero (outside every band)
-  auto load_x = [&](int mrow, T (&dst)[NT]) {
+  // Contraction step s of a 64-photon-number chunk at mb gives k-slot kq the photon
+  // number mb + 4 s + kq, so each lane walks its probe's row of F with stride 4 across
+  // the wave's whole (contiguous) share of the tile: F[d][m + 4] = F[d][m] mu^4 r4[m],
+  // r4[m] = 1 / ((m+1)(m+2)(m+3)(m+4)).  A lane takes a fresh anchor where its band
+  // starts and every 16 chunks.  X rows beyond M-1 are clamped: F is zero there.
+  auto load_step = [&](int mrow, T (&dst)[NT], double& r) {
     const int m = mrow < M - 1 ? mrow : M - 1;
-    const T* xr = X + (size_t)m * Npad + i;
+    const unsigned base = (unsigned)m * (unsigned)Npad + (unsigned)i;
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) dst[nt] = xr[nt * 16];
+    for (int nt = 0; nt < NT; ++nt) dst[nt] = X[base + 16u * nt];
+    r = pv.r4[mrow];
   };
-  constexpr int stride = kChunkM * KS;
-  int mb = mlo + kChunkM * wv;
+  const int nch = mhi >= mlo ? (mhi - mlo) / kChunkM + 1 : 0;
+  const int c0 = (nch * wv) / KS;
+  const int c1 = (nch * (wv + 1)) / KS;
+  const double mu4 = (mu * mu) * (mu * mu);
   T xb[PF][NT];
-  if (mb <= mhi) {
+  double rb[PF];
+  if (c0 < c1) {
 #pragma unroll
-    for (int p = 0; p < PF; ++p) load_x(mb + 16 * kq + p, xb[p]);
+    for (int q = 0; q < PF; ++q) load_step(mlo + kChunkM * c0 + 4 * q + kq, xb[q], rb[q]);
   }
-  for (; mb <= mhi; mb += stride) {
-    const int mbn = mb + stride;
-    const bool more = mbn <= mhi;
-    const int ms = mb + 16 * kq;
-    double p = 0.0;
-    if (ms <= bhi && ms + 15 >= blo) p = poisson_pmf(ms, mu);
+  double p = 0.0;
+  for (int c = c0; c < c1; ++c) {
+    const int mb = mlo + kChunkM * c;
+    const bool more = c + 1 < c1;
+    const int ma = mb + kq;
+    if ((p == 0.0 || ((c - c0) & 15) == 0) && ma <= bhi && ma + 60 >= blo) p = poisson_pmf(ma, mu);
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const int m = ms + s;
+    for (int st = 0; st < 16; ++st) {
+      const int m = ma + 4 * st;
       double f = (m >= blo && m <= bhi) ? p : 0.0;
       f = (m == lumpm && m >= blo && m <= bhi) ? tl : f;
-      p *= mu / (double)(m + 1);
+      p *= mu4 * rb[st % PF];
       const T a = (T)f;
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) acc[nt] = Acc<T>::mfma(a, xb[s % PF][nt], acc[nt]);
-      if (s + PF < 16) load_x(ms + s + PF, xb[s % PF]);
-      else if (more) load_x(mbn + 16 * kq + s + PF - 16, xb[s % PF]);
+      for (int nt = 0; nt < NT; ++nt) acc[nt] = Acc<T>::mfma(a, xb[st % PF][nt], acc[nt]);
+      if (st + PF < 16) load_step(m + 4 * PF, xb[st % PF], rb[st % PF]);
+      else if (more) load_step(m + 4 * PF, xb[st % PF], rb[st % PF]);
     }
   }
   reduce_tiles<T, NT>(acc, S, LDT, wv, i, kq);
@@ -349,42 +357,66 @@ __global__ __launch_bounds__(64 * KS) void ftr_kernel(ProbView pv, Bufs<T> b, So
   // probes beyond dhi are clamped: their generated F entries are zero
   auto load_r = [&](int drow, T (&dst)[NT]) {
     const int dd = drow < dhi ? drow : dhi;
-    const T* rr = R + (size_t)(dd > 0 ? dd : 0) * Npad + i;
+    const unsigned base = (unsigned)(dd > 0 ? dd : 0) * (unsigned)Npad + (unsigned)i;
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) dst[nt] = rr[nt * 16];
+    for (int nt = 0; nt < NT; ++nt) dst[nt] = R[base + 16u * nt];
   };
   const int nchunks = dhi >= dlo ? (dhi - dlo) / kChunkD + 1 : 0;
   const int rounds = (nchunks + KS - 1) / KS;
   constexpr int stride = kChunkD * KS;
+  // the tile's 16 photon numbers are shared by every probe: 1/(m+1) once per workgroup
+  double inv[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) inv[j] = pv.rinv[m0 + j + 1];
+
+  // generator state of one probe (lane) for a chunk: F[d][m0 + j], j = 0..15.  The
+  // probe parameters are loaded one round before the anchor is formed from them.
+  struct Gen {
+    double mu, tl, p;
+    int blo, bhi;
+  };
+  const double* __restrict__ anc = pv.anchors + pv.mt_aoff[mt];
+  auto gen_params = [&](int dcc) {
+    Gen g{0.0, 0.0, 0.0, 1, 0};
+    const int d = dcc + lane;
+    if (d <= dhi) {
+      g.mu = pv.mu[d];
+      g.blo = pv.lo[d];
+      g.bhi = pv.hi[d];
+      g.tl = pv.lump ? pv.tail[d] : 0.0;
+      g.p = anc[d - dlo];  // F[d][m0] from the setup table (0 where the band misses the tile)
+    }
+    return g;
+  };
+  auto gen_anchor = [&](Gen&) {};
+  auto gen_step = [&](Gen& g, int j) -> double {
+    const int m = m0 + j;
+    double f = (m >= g.blo && m <= g.bhi) ? g.p : 0.0;
+    f = (m == lumpm && m >= g.blo && m <= g.bhi) ? g.tl : f;
+    g.p *= g.mu * inv[j];
+    return f;
+  };
+
   int dc = dlo + kChunkD * wv;
   T rb[PF][NT];
 #pragma unroll
   for (int p = 0; p < PF; ++p) load_r(dc + 16 * kq + p, rb[p]);
+  double vals[16];
+  Gen gn;  // parameters of the chunk after the one being generated
+  if (rounds > 0) {
+    Gen g = gen_params(dc);
+    gen_anchor(g);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) vals[j] = gen_step(g, j);
+    gn = gen_params(dc + stride);
+  }
   for (int rd = 0; rd < rounds; ++rd, dc += stride) {
     const int dcn = dc + stride;
-    {
-      const int d = dc + lane;
-      double mu = 0.0, tl = 0.0;
-      int blo = 1, bhi = 0;
-      bool any = false;
-      if (d <= dhi) {
-        mu = pv.mu[d];
-        blo = pv.lo[d];
-        bhi = pv.hi[d];
-        tl = pv.lump ? pv.tail[d] : 0.0;
-        any = (m0 <= bhi) && (m0 + 15 >= blo);
-      }
-      double p = any ? poisson_pmf(m0, mu) : 0.0;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int m = m0 + j;
-        double f = (m >= blo && m <= bhi) ? p : 0.0;
-        f = (m == lumpm && m >= blo && m <= bhi) ? tl : f;
-        Ft[wv][lane][j] = f;
-        p *= mu / (double)(m + 1);
-      }
-    }
+    for (int j = 0; j < 16; ++j) Ft[wv][lane][j] = vals[j];
     __syncthreads();
+    // the next chunk's F values are generated between this chunk's MFMAs
+    Gen g = gn;
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const T a = (T)Ft[wv][16 * kq + s][i];
@@ -392,7 +424,12 @@ __global__ __launch_bounds__(64 * KS) void ftr_kernel(ProbView pv, Bufs<T> b, So
       for (int nt = 0; nt < NT; ++nt) acc[nt] = Acc<T>::mfma(a, rb[s % PF][nt], acc[nt]);
       if (s + PF < 16) load_r(dc + 16 * kq + s + PF, rb[s % PF]);
       else load_r(dcn + 16 * kq + s + PF - 16, rb[s % PF]);
+      if (s == 1) gen_anchor(g);
+      if (s == 2) gn = gen_params(dcn + stride);
+      if (s >= 2) vals[s - 2] = gen_step(g, s - 2);
     }
+    vals[14] = gen_step(g, 14);
+    vals[15] = gen_step(g, 15);
     __syncthreads();
   }
   reduce_tiles<T, NT>(acc, S, LDT, wv, i, kq);
@@ -621,9 +658,31 @@ __global__ void setup_bands_kernel(const double* mu, int D, int M, double tau, i
   hi[d] = h;
 }
 
-__global__ void fill_rinv_kernel(double* rinv, int n) {
+__global__ void fill_rinv_kernel(double* rinv, double* r4, int n) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m < n) rinv[m] = m == 0 ? 0.0 : 1.0 / (double)m;
+  if (m >= n) return;
+  rinv[m] = m == 0 ? 0.0 : 1.0 / (double)m;
+  const double a = (double)(m + 1) * (double)(m + 4);  // exact below 2^53
+  const double b = (double)(m + 2) * (double)(m + 3);
+  r4[m] = 1.0 / (a * b);
+}
+
+// F[d][16 t] for every probe d whose band is considered by row tile t (0 where the
+// band misses the tile): the transposed product's anchors, fixed for the whole solve.
+__global__ void setup_anchors_kernel(const double* mu, const int* lo, const int* hi, const int* mt_dlo,
+                                     const int* mt_dhi, const long long* mt_aoff, int n_mt, int M, int lump,
+                                     const double* tail, double* anchors) {
+  const int t = blockIdx.x;
+  if (t >= n_mt) return;
+  const int dlo = mt_dlo[t], dhi = mt_dhi[t];
+  const int m0 = 16 * t;
+  double* out = anchors + mt_aoff[t];
+  for (int d = dlo + (int)threadIdx.x; d <= dhi; d += (int)blockDim.x) {
+    const int blo = lo[d], bhi = hi[d];
+    double v = 0.0;
+    if (m0 <= bhi && m0 + 15 >= blo) v = (lump && m0 == M - 1) ? tail[d] : poisson_pmf(m0, mu[d]);
+    out[d - dlo] = v;
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -752,8 +811,15 @@ hipError_t launch_setup_bands(const double* mu, int D, int M, double tau, int lu
   return hipGetLastError();
 }
 
-hipError_t launch_fill_rinv(double* rinv, int n, hipStream_t s) {
-  hipLaunchKernelGGL(fill_rinv_kernel, dim3((n + 255) / 256), dim3(256), 0, s, rinv, n);
+hipError_t launch_fill_rinv(double* rinv, double* r4, int n, hipStream_t s) {
+  hipLaunchKernelGGL(fill_rinv_kernel, dim3((n + 255) / 256), dim3(256), 0, s, rinv, r4, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_setup_anchors(const ProbView& pv, const long long* mt_aoff, double* anchors, hipStream_t s) {
+  const int n_mt = (pv.M + 15) / 16;
+  hipLaunchKernelGGL(setup_anchors_kernel, dim3(n_mt), dim3(256), 0, s, pv.mu, pv.lo, pv.hi, pv.mt_dlo, pv.mt_dhi,
+                     mt_aoff, n_mt, pv.M, pv.lump, pv.tail, anchors);
   return hipGetLastError();
 }
 

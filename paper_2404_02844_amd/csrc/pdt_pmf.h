@@ -83,7 +83,7 @@ __device__ inline double poisson_upper_tail(double mu, int k0) {
       const double t = sum + p;
       comp += (fabs(sum) >= fabs(p)) ? (sum - t) + p : (p - t) + sum;
       sum = t;
-      if (p < 1e-22 * sum) break;
+      if (p <= 1e-22 * sum) break;  // also ends a sum whose first term underflowed
       ++m;
       p = ((m & 255) == 0) ? poisson_pmf(m, mu) : p * (mu / (double)m);
     }
@@ -96,7 +96,7 @@ __device__ inline double poisson_upper_tail(double mu, int k0) {
     const double t = sum + p;
     comp += (fabs(sum) >= fabs(p)) ? (sum - t) + p : (p - t) + sum;
     sum = t;
-    if (p < 1e-22 * sum) break;
+    if (p <= 1e-22 * sum) break;  // also ends a sum whose first term underflowed
     const double ratio = (double)m / mu;
     --m;
     if (m < 0) break;

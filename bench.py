@@ -83,7 +83,7 @@ def main():
     Pi = torch.zeros((M, N), dtype=torch.float64, device=dev)
 
     if args.kernels_only:
-        for prec in (_pdt.PDT_FP64, _pdt.PDT_FP32):
+        for prec in (_pdt.PDT_FP64, _pdt.PDT_FP32, _pdt.PDT_MIXED):
             pb.solve(Pi, precision=prec, max_iters=200)
             for kern in (0, 1, 2):
                 _pdt.pdt_replay_kernel(pb.handle, kern, prec, 200)
@@ -126,6 +126,10 @@ def main():
             f"relobj={(r['objective'] - f_ref) / f_ref:.2e}")
     fp32 = solve(_pdt.PDT_FP32, 1e-4)
     log(f"[bench] fp32 solve: iters={fp32['iters']} wall={fp32['wall']:.3f}s converged={fp32['converged']}")
+    mixed = [solve(_pdt.PDT_MIXED, args.tol) for _ in range(max(1, args.steps))]
+    for r in mixed:
+        log(f"[bench] mixed solve: iters={r['iters']} (fp64 refinement {r['refine_iters']}) wall={r['wall']:.3f}s "
+            f"converged={r['converged']} relobj={(r['objective'] - f_ref) / f_ref:.2e}")
 
     # dominant kernel: the transposed band product + projected step, timed on the stream
     # it is launched on
@@ -140,6 +144,15 @@ def main():
         e1.record(stream)
         e1.synchronize()
         times[name] = e0.elapsed_time(e1) / reps * 1e-3
+    for kern, name in ((0, "ftr"), (1, "fx"), (3, "iteration")):
+        _pdt.pdt_replay_kernel(pb.handle, kern, _pdt.PDT_MIXED, 10)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        _pdt.pdt_replay_kernel(pb.handle, kern, _pdt.PDT_MIXED, reps)
+        e1.record(stream)
+        e1.synchronize()
+        times["mixed_" + name] = e0.elapsed_time(e1) / reps * 1e-3
+    log("[bench] kernel times (us): " + " ".join(f"{k}={v * 1e6:.1f}" for k, v in times.items()))
     flops = 2.0 * nnz * N
     achieved = flops / times["ftr"] / 1e12
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
@@ -170,6 +183,13 @@ def main():
         "time_to_tol_s": float(np.median([r["wall"] for r in runs])),
         "iters_to_tol": int(np.median([r["iters"] for r in runs])),
         "f_ref": f_ref,
+        "mixed": {"time_to_tol_s": float(np.median([r["wall"] for r in mixed])),
+                  "iters": int(np.median([r["iters"] for r in mixed])),
+                  "refine_iters": int(np.median([r["refine_iters"] for r in mixed])),
+                  "converged": int(min(r["converged"] for r in mixed)), "tol": args.tol,
+                  "relobj": float(max((r["objective"] - f_ref) / f_ref for r in mixed)),
+                  "speedup_vs_fp64": float(np.median([r["wall"] for r in runs]) /
+                                           np.median([r["wall"] for r in mixed]))},
         "fp32": {"time_to_tol_s": fp32["wall"], "iters": fp32["iters"], "tol": 1e-4,
                  "converged": fp32["converged"], "relobj": (fp32["objective"] - f_ref) / f_ref},
         "roofline": roofline,

@@ -46,9 +46,12 @@ typedef enum {
 } pdt_status;
 
 typedef enum {
-  PDT_FP64 = 0,       /* products and iterates in FP64 (FP64 MFMA) */
-  PDT_FP32 = 1,       /* products and iterates in FP32 (FP32 MFMA), FP64 objective */
-  PDT_MIXED_BF16 = 2  /* reserved: BF16 products with FP32 accumulation + FP64 refinement */
+  PDT_FP64 = 0,  /* products and iterates in FP64 (FP64 MFMA) */
+  PDT_FP32 = 1,  /* products and iterates in FP32 (FP32 MFMA), FP64 objective */
+  PDT_MIXED = 2  /* FP32 MFMA products on FP64 iterates: F X is kept in FP64 and updated by
+                    F (X_new - X_cur) in FP32, resynchronised exactly every 64 iterations;
+                    once a 64-iteration chunk lowers f by < 1e-10 relative the solve
+                    continues in FP64 (the refinement sweep) to the requested tolerance */
 } pdt_precision;
 
 typedef enum {
@@ -109,6 +112,7 @@ typedef struct {
   double L_used;          /* Lipschitz constant used for the step */
   double seconds;         /* wall time of the call */
   int converged;          /* 1 if the tolerance test was met */
+  int64_t refine_iters;   /* PDT_MIXED: iterations of the FP64 refinement (included in iters) */
 } pdt_solve_info;
 
 /*

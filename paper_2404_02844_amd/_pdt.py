@@ -21,7 +21,7 @@ PDT_ERR_NUMERIC = 5
 
 PDT_FP64 = 0
 PDT_FP32 = 1
-PDT_MIXED_BF16 = 2
+PDT_MIXED = 2
 
 PDT_TAIL_TRUNCATE = 0
 PDT_TAIL_LUMP = 1
@@ -55,7 +55,7 @@ class pdt_solve_opts(ctypes.Structure):
 class pdt_solve_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("rejects", ctypes.c_int64), ("objective", ctypes.c_double),
                 ("kkt", ctypes.c_double), ("L_used", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("converged", ctypes.c_int)]
+                ("converged", ctypes.c_int), ("refine_iters", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

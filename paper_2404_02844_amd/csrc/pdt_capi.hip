@@ -9,6 +9,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "pdt.h"
@@ -99,11 +100,11 @@ struct Instance {
   SolverState* st = nullptr;
   SolverState* st_eval = nullptr;
   double* scalar = nullptr;
-  // captured chunk of iterations, reused while (precision, step, history) match
-  hipGraphExec_t graph = nullptr;
-  int graph_prec = -1;
-  double graph_step = 0.0;
-  double* graph_hist = nullptr;
+  // captured chunks of iterations, one slot per kernel variant, reused while
+  // (step, history) match
+  hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
+  double graph_step[3] = {0.0, 0.0, 0.0};
+  double* graph_hist[3] = {nullptr, nullptr, nullptr};
 };
 
 }  // namespace
@@ -382,79 +383,119 @@ double eval_fp64(pdt_problem_s* pb, Instance& I, bool grad, double* kkt_out) {
 
 constexpr int64_t kGraphIters = 64;
 
-template <typename T>
-void enqueue_iters(const ProbView& pv, const Bufs<T>& b, SolverState* st, double step, int64_t n, hipStream_t s) {
+// kernel variants of the iteration: storage / MFMA type
+enum Variant { VAR_FP64 = 0, VAR_FP32 = 1, VAR_MIXED = 2 };
+
+template <typename TS, typename TC>
+void enqueue_iters(const ProbView& pv, const Bufs<TS>& b, SolverState* st, double step, int64_t n, bool delta,
+                   hipStream_t s) {
   const int nfx = fx_num_waves(pv);
   for (int64_t k = 0; k < n; ++k) {
-    HIPCHK(launch_ftr<T>(pv, b, st, FTR_STEP, step, s));
-    HIPCHK(launch_fx<T>(pv, b, st, FX_ITER, s));
+    HIPCHK((launch_ftr<TS, TC>(pv, b, st, FTR_STEP, step, s)));
+    HIPCHK((launch_fx<TS, TC>(pv, b, st, delta ? FX_DELTA : FX_ITER, s)));
     HIPCHK(launch_decide(b.partials, nfx, st, b.history, DEC_ITER, s));
   }
 }
 
-void drop_graph(Instance& I) {
-  if (I.graph) (void)hipGraphExecDestroy(I.graph);
-  I.graph = nullptr;
-  I.graph_prec = -1;
+void drop_graphs(Instance& I) {
+  for (int v = 0; v < 3; ++v) {
+    if (I.graph[v]) (void)hipGraphExecDestroy(I.graph[v]);
+    I.graph[v] = nullptr;
+  }
 }
 
-// Iterations are launched kGraphIters at a time from one captured graph; kernels read
-// the device state and return at once after it says done, so surplus launches of the
-// last chunk cost only their launch.
+// One graph = kGraphIters iterations of a variant.  The mixed variant forms F X_new by
+// the FP32 delta F (X_new - X_cur) on FP64 storage, so it ends with an exact FP64
+// forward product of the current iterate that removes the drift of those updates.
+template <typename TS, typename TC>
+hipGraphExec_t get_graph(pdt_problem_s* pb, Instance& I, int var, const Bufs<TS>& b, double step) {
+  if (I.graph[var] && I.graph_step[var] == step && I.graph_hist[var] == b.history) return I.graph[var];
+  if (I.graph[var]) (void)hipGraphExecDestroy(I.graph[var]);
+  I.graph[var] = nullptr;
+  // recorded on the library's own stream (the caller's may be the legacy default
+  // stream, which cannot be captured); replayed on the caller's stream
+  if (!pb->capture) HIPCHK(hipStreamCreateWithFlags(&pb->capture, hipStreamNonBlocking));
+  hipStream_t cs = pb->capture;
+  const ProbView pv = view_of(I);
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  try {
+    enqueue_iters<TS, TC>(pv, b, I.st, step, kGraphIters, var == VAR_MIXED, cs);
+    if (var == VAR_MIXED) HIPCHK((launch_fx<TS, TS>(pv, b, I.st, FX_EVAL, cs)));
+  } catch (...) {
+    (void)hipStreamEndCapture(cs, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  HIPCHK(hipStreamEndCapture(cs, &g));
+  hipGraphExec_t ge = nullptr;
+  hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIPCHK(e);
+  I.graph[var] = ge;
+  I.graph_step[var] = step;
+  I.graph_hist[var] = b.history;
+  return ge;
+}
+
+// Runs iterations of one variant from the current device state until it reports done,
+// max_iters is reached, or (stagnate = true) a chunk lowers f by less than 1e-10
+// relative.  Returns the state read after the last chunk.
+template <typename TS, typename TC>
+SolverState run_chunks(pdt_problem_s* pb, Instance& I, int var, const Bufs<TS>& b, double step, int64_t budget,
+                       bool stagnate) {
+  hipStream_t s = pb->stream;
+  const ProbView pv = view_of(I);
+  SolverState h = read_state(s, I.st);
+  int64_t launched = 0;
+  while (launched < budget && !h.done) {
+    const double f0 = h.f_cur;
+    if (budget - launched >= kGraphIters) {
+      HIPCHK(hipGraphLaunch(get_graph<TS, TC>(pb, I, var, b, step), s));
+      launched += kGraphIters;
+    } else {
+      const int64_t n = budget - launched;
+      enqueue_iters<TS, TC>(pv, b, I.st, step, n, var == VAR_MIXED, s);
+      if (var == VAR_MIXED) HIPCHK((launch_fx<TS, TS>(pv, b, I.st, FX_EVAL, s)));
+      launched += n;
+    }
+    h = read_state(s, I.st);
+    if (stagnate && f0 - h.f_cur <= 1e-10 * h.f_cur) break;
+  }
+  return h;
+}
+
 template <typename T>
-void run_loop(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double step, int prec, SolverState& out) {
+void run_loop(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double step, int var, SolverState& out) {
   hipStream_t s = pb->stream;
   const ProbView pv = view_of(I);
   Work<T>& w = work_of<T>(I);
   Bufs<T> b = bufs_of(I, w, o.history);
   HIPCHK(launch_fx<T>(pv, b, I.st, FX_INIT, s));
   HIPCHK(launch_decide(I.partials, fx_num_waves(pv), I.st, nullptr, DEC_INIT, s));
-  const bool use_graph = o.max_iters >= kGraphIters;
-  if (use_graph && !(I.graph && I.graph_prec == prec && I.graph_step == step && I.graph_hist == o.history)) {
-    drop_graph(I);
-    // recorded on the library's own stream (the caller's may be the legacy default
-    // stream, which cannot be captured); replayed on the caller's stream
-    if (!pb->capture) HIPCHK(hipStreamCreateWithFlags(&pb->capture, hipStreamNonBlocking));
-    hipStream_t cs = pb->capture;
-    hipGraph_t g = nullptr;
-    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    try {
-      enqueue_iters<T>(pv, b, I.st, step, kGraphIters, cs);
-    } catch (...) {
-      (void)hipStreamEndCapture(cs, &g);
-      if (g) (void)hipGraphDestroy(g);
-      throw;
-    }
-    HIPCHK(hipStreamEndCapture(cs, &g));
-    hipGraphExec_t ge = nullptr;
-    hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    HIPCHK(e);
-    I.graph = ge;
-    I.graph_prec = prec;
-    I.graph_step = step;
-    I.graph_hist = o.history;
-  }
-  int64_t launched = 0;
-  while (launched < o.max_iters) {
-    if (use_graph) {
-      HIPCHK(hipGraphLaunch(I.graph, s));
-      launched += kGraphIters;
-    } else {
-      const int64_t n = o.max_iters - launched;
-      enqueue_iters<T>(pv, b, I.st, step, n, s);
-      launched += n;
-    }
-    SolverState h = read_state(s, I.st);
-    if (h.done) break;
-  }
-  out = read_state(s, I.st);
+  out = run_chunks<T, T>(pb, I, var, b, step, o.max_iters, false);
+}
+
+// Mixed path: FP32 products on FP64 iterates until progress stalls, then the FP64
+// refinement continues from the same state to the requested tolerance.
+void run_mixed(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double step, SolverState& out,
+               int64_t& refine_iters) {
+  hipStream_t s = pb->stream;
+  const ProbView pv = view_of(I);
+  Bufs<double> b = bufs_of(I, I.w64, o.history);
+  HIPCHK(launch_fx<double>(pv, b, I.st, FX_INIT, s));
+  HIPCHK(launch_decide(I.partials, fx_num_waves(pv), I.st, nullptr, DEC_INIT, s));
+  SolverState h = run_chunks<double, float>(pb, I, VAR_MIXED, b, step, o.max_iters, true);
+  const int64_t mixed_iters = h.iter;
+  if (!h.done) h = run_chunks<double, double>(pb, I, VAR_FP64, b, step, o.max_iters - mixed_iters, false);
+  refine_iters = h.iter - mixed_iters;
+  out = h;
 }
 
 }  // namespace
 
 namespace {
-template <typename T>
+template <typename T, typename TC = T>
 void replay_impl(pdt_problem_s* pb, Instance& I, int kernel, int64_t reps) {
   hipStream_t s = pb->stream;
   const ProbView pv = view_of(I);
@@ -472,8 +513,9 @@ void replay_impl(pdt_problem_s* pb, Instance& I, int kernel, int64_t reps) {
   HIPCHK(hipMemcpyAsync(I.st_eval, &s0, sizeof(s0), hipMemcpyHostToDevice, s));
   const double step = 1.0 / I.L_hat;
   for (int64_t r = 0; r < reps; ++r) {
-    if (kernel == 0 || kernel == 3) HIPCHK(launch_ftr<T>(pv, b, I.st_eval, FTR_STEP, step, s));
-    if (kernel == 1 || kernel == 3) HIPCHK(launch_fx<T>(pv, b, I.st_eval, FX_ITER, s));
+    const int fxmode = std::is_same<T, TC>::value ? FX_ITER : FX_DELTA;  // the mixed kernel is delta-only
+    if (kernel == 0 || kernel == 3) HIPCHK((launch_ftr<T, TC>(pv, b, I.st_eval, FTR_STEP, step, s)));
+    if (kernel == 1 || kernel == 3) HIPCHK((launch_fx<T, TC>(pv, b, I.st_eval, fxmode, s)));
     if (kernel == 2 || kernel == 3)
       HIPCHK(launch_decide(I.partials, fx_num_waves(pv), I.st_eval, nullptr, DEC_ITER, s));
   }
@@ -520,7 +562,7 @@ pdt_status pdt_make_problem(const pdt_problem_desc* descs, int64_t n_instances, 
 void pdt_destroy_problem(pdt_problem_t problem) {
   if (!problem) return;
   (void)hipStreamSynchronize(problem->stream);
-  for (Instance& I : problem->inst) drop_graph(I);
+  for (Instance& I : problem->inst) drop_graphs(I);
   if (problem->capture) (void)hipStreamDestroy(problem->capture);
   problem->arena.release();
   delete problem;
@@ -579,7 +621,7 @@ pdt_status pdt_solve(pdt_problem_t pb, double* Pi, const pdt_solve_opts* opts, p
   if (o.max_iters < 0) return set_err(PDT_ERR_INVALID_ARG, "max_iters must be >= 0");
   if (!std::isfinite(o.step_L) || o.step_L < 0) return set_err(PDT_ERR_INVALID_ARG, "step_L must be >= 0");
   if (o.init != PDT_INIT_UNIFORM && o.init != PDT_INIT_USER) return set_err(PDT_ERR_INVALID_ARG, "bad init");
-  if (o.precision != PDT_FP64 && o.precision != PDT_FP32)
+  if (o.precision != PDT_FP64 && o.precision != PDT_FP32 && o.precision != PDT_MIXED)
     return set_err(PDT_ERR_INVALID_ARG, "precision not supported");
   if (!std::isfinite(o.rel_obj_tol) || o.rel_obj_tol < 0 || !std::isfinite(o.f_star))
     return set_err(PDT_ERR_INVALID_ARG, "bad tolerance");
@@ -601,12 +643,12 @@ pdt_status pdt_solve(pdt_problem_t pb, double* Pi, const pdt_solve_opts* opts, p
     const double f_star = o.f_star > 0 ? o.f_star : 0.0;
     init_state(s, I.st, o.max_iters, f_star, o.rel_obj_tol);
     SolverState fin;
-    int ix_final = 0;
-    if (o.precision == PDT_FP64) {
-      run_loop<double>(pb, I, o, step, PDT_FP64, fin);
-      ix_final = fin.ix_cur;
-      if (ix_final != 0)
-        HIPCHK(hipMemcpyAsync(I.w64.X[0], I.w64.X[ix_final], M * Np * sizeof(double), hipMemcpyDeviceToDevice, s));
+    int64_t refine_iters = 0;
+    if (o.precision == PDT_FP64 || o.precision == PDT_MIXED) {
+      if (o.precision == PDT_FP64) run_loop<double>(pb, I, o, step, VAR_FP64, fin);
+      else run_mixed(pb, I, o, step, fin, refine_iters);
+      if (fin.ix_cur != 0)
+        HIPCHK(hipMemcpyAsync(I.w64.X[0], I.w64.X[fin.ix_cur], M * Np * sizeof(double), hipMemcpyDeviceToDevice, s));
     } else {
       if (!I.P32) {
         I.P32 = A.alloc<float>((size_t)I.D * Np);
@@ -614,7 +656,7 @@ pdt_status pdt_solve(pdt_problem_t pb, double* Pi, const pdt_solve_opts* opts, p
       }
       ensure_work<float>(A, I, I.w32, I.P32);
       HIPCHK(launch_convert_pad<double, float>(I.w64.X[0], I.w32.X[0], (long long)M, (int)Np, (int)Np, (int)Np, s));
-      run_loop<float>(pb, I, o, step, PDT_FP32, fin);
+      run_loop<float>(pb, I, o, step, VAR_FP32, fin);
       HIPCHK(launch_convert_pad<float, double>(I.w32.X[fin.ix_cur], I.w64.X[0], (long long)M, (int)Np, (int)Np,
                                                (int)Np, s));
     }
@@ -632,6 +674,7 @@ pdt_status pdt_solve(pdt_problem_t pb, double* Pi, const pdt_solve_opts* opts, p
       info->L_used = L;
       info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       info->converged = conv ? 1 : 0;
+      info->refine_iters = refine_iters;
     }
     if (!std::isfinite(f)) return set_err(PDT_ERR_NUMERIC, "objective is not finite");
     if (f_star > 0 && o.rel_obj_tol > 0 && !conv)
@@ -655,6 +698,9 @@ pdt_status pdt_replay_kernel(pdt_problem_t pb, int kernel, int precision, int64_
     } else if (precision == PDT_FP32) {
       if (!I.w32.ready) return set_err(PDT_ERR_INVALID_ARG, "solve in FP32 once before replaying");
       replay_impl<float>(pb, I, kernel, reps);
+    } else if (precision == PDT_MIXED) {
+      if (!I.w64.ready) return set_err(PDT_ERR_INVALID_ARG, "solve once before replaying");
+      replay_impl<double, float>(pb, I, kernel, reps);
     } else {
       return set_err(PDT_ERR_INVALID_ARG, "precision not supported");
     }

@@ -28,7 +28,7 @@ constexpr int kChunkD = 64;       // probes per transposed-product chunk
 constexpr int kMaxNT = 12;        // outcome columns up to 192
 constexpr int kWave = 64;
 
-enum FxMode { FX_ITER = 0, FX_INIT = 1, FX_EVAL = 2 };
+enum FxMode { FX_ITER = 0, FX_INIT = 1, FX_EVAL = 2, FX_DELTA = 3 };
 enum FtrMode { FTR_STEP = 0, FTR_GRAD = 1 };
 enum DecideMode { DEC_ITER = 0, DEC_INIT = 1, DEC_EVAL = 2 };
 
@@ -83,10 +83,11 @@ struct Bufs {
 };
 
 // Launchers (pdt_kernels.hip).
-template <typename T>
-hipError_t launch_fx(const ProbView& pv, const Bufs<T>& b, SolverState* st, int mode, hipStream_t s);
-template <typename T>
-hipError_t launch_ftr(const ProbView& pv, const Bufs<T>& b, SolverState* st, int mode, double step,
+// TS: storage type, TC: MFMA operand type (TC = TS, or float products on FP64 storage)
+template <typename TS, typename TC = TS>
+hipError_t launch_fx(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode, hipStream_t s);
+template <typename TS, typename TC = TS>
+hipError_t launch_ftr(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode, double step,
                       hipStream_t s);
 hipError_t launch_decide(const double* partials, int n, SolverState* st, double* history, int mode,
                          hipStream_t s);

@@ -23,6 +23,7 @@
 
 #include <cfloat>
 #include <cmath>
+#include <type_traits>
 
 #include "pdt_internal.h"
 #include "pdt_pmf.h"
@@ -180,10 +181,14 @@ __device__ __forceinline__ void reduce_tiles(const AccT (&acc)[NT], double* S, i
   }
 }
 
-template <typename T, int NT>
-__global__ __launch_bounds__(64 * KS) void fx_kernel(ProbView pv, Bufs<T> b, SolverState* st, int mode) {
-  if (mode == FX_ITER && st->done) return;
-  typedef typename Acc<T>::type AccT;
+// TS: storage type of X, O, R, P.  TC: MFMA operand type (TS, or float under TS = double
+// for the mixed path, whose forward product works on X_new - X_cur: FX_DELTA).
+template <typename TS, typename TC, int NT>
+__global__ __launch_bounds__(64 * KS) void fx_kernel(ProbView pv, Bufs<TS> b, SolverState* st, int mode) {
+  if ((mode == FX_ITER || mode == FX_DELTA) && st->done) return;
+  typedef TS T;
+  typedef typename Acc<TC>::type AccT;
+  const bool iter = mode == FX_ITER || mode == FX_DELTA;
   constexpr int LDT = 16 * NT + 1;
   __shared__ double S[16 * LDT];
   __shared__ double red[KS];
@@ -196,10 +201,13 @@ __global__ __launch_bounds__(64 * KS) void fx_kernel(ProbView pv, Bufs<T> b, Sol
   const int M = pv.M, D = pv.D, N = pv.N, Npad = pv.Npad;
 
   const int ix_cur = st->ix_cur;
-  const int ix_x = (mode == FX_ITER) ? st->ix_new : ix_cur;
+  const int ix_x = iter ? st->ix_new : ix_cur;
   const T* __restrict__ X = b.X[ix_x];
+  const T* __restrict__ Xcur = b.X[ix_cur];
   T* __restrict__ O = b.O[ix_x];
   const T* __restrict__ Ocur = b.O[ix_cur];
+  // the mixed instantiation (float products on double storage) always forms the delta
+  constexpr bool delta = !std::is_same<TS, TC>::value;
 
   const int d0 = tile << 4;
   const int d = d0 + i;
@@ -221,18 +229,23 @@ __global__ __launch_bounds__(64 * KS) void fx_kernel(ProbView pv, Bufs<T> b, Sol
   // the wave's whole (contiguous) share of the tile: F[d][m + 4] = F[d][m] mu^4 r4[m],
   // r4[m] = 1 / ((m+1)(m+2)(m+3)(m+4)).  A lane takes a fresh anchor where its band
   // starts and every 16 chunks.  X rows beyond M-1 are clamped: F is zero there.
-  auto load_step = [&](int mrow, T (&dst)[NT], double& r) {
+  auto load_step = [&](int mrow, TC (&dst)[NT], double& r) {
     const int m = mrow < M - 1 ? mrow : M - 1;
     const unsigned base = (unsigned)m * (unsigned)Npad + (unsigned)i;
+    if constexpr (delta) {
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) dst[nt] = X[base + 16u * nt];
+      for (int nt = 0; nt < NT; ++nt) dst[nt] = (TC)(X[base + 16u * nt] - Xcur[base + 16u * nt]);
+    } else {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) dst[nt] = (TC)X[base + 16u * nt];
+    }
     r = pv.r4[mrow];
   };
   const int nch = mhi >= mlo ? (mhi - mlo) / kChunkM + 1 : 0;
   const int c0 = (nch * wv) / KS;
   const int c1 = (nch * (wv + 1)) / KS;
   const double mu4 = (mu * mu) * (mu * mu);
-  T xb[PF][NT];
+  TC xb[PF][NT];
   double rb[PF];
   if (c0 < c1) {
 #pragma unroll
@@ -250,18 +263,18 @@ __global__ __launch_bounds__(64 * KS) void fx_kernel(ProbView pv, Bufs<T> b, Sol
       double f = (m >= blo && m <= bhi) ? p : 0.0;
       f = (m == lumpm && m >= blo && m <= bhi) ? tl : f;
       p *= mu4 * rb[st % PF];
-      const T a = (T)f;
+      const TC a = (TC)f;
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) acc[nt] = Acc<T>::mfma(a, xb[st % PF][nt], acc[nt]);
+      for (int nt = 0; nt < NT; ++nt) acc[nt] = Acc<TC>::mfma(a, xb[st % PF][nt], acc[nt]);
       if (st + PF < 16) load_step(m + 4 * PF, xb[st % PF], rb[st % PF]);
       else if (more) load_step(m + 4 * PF, xb[st % PF], rb[st % PF]);
     }
   }
-  reduce_tiles<T, NT>(acc, S, LDT, wv, i, kq);
+  reduce_tiles<TC, NT>(acc, S, LDT, wv, i, kq);
 
   // epilogue: wave wv finishes probe rows 4 wv + kq
   T beta_acc = 0;
-  if (mode == FX_ITER) {
+  if (iter) {
     const double t = st->t;
     const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
     const double tnn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * tn * tn));
@@ -274,15 +287,16 @@ __global__ __launch_bounds__(64 * KS) void fx_kernel(ProbView pv, Bufs<T> b, Sol
     for (int nt = 0; nt < NT; ++nt) {
       const int n = nt * 16 + i;
       const size_t off = (size_t)dd * Npad + n;
-      const T o = (T)S[(4 * wv + kq) * LDT + n];
+      const T oc_ = iter ? Ocur[off] : (T)0;
+      const T o = delta ? oc_ + (T)S[(4 * wv + kq) * LDT + n] : (T)S[(4 * wv + kq) * LDT + n];
       const T pv_ = b.P[off];
       O[off] = o;
       if (n < N) {
         const double e = (double)o - (double)pv_;
         part += e * e;
       }
-      if (mode == FX_ITER) {
-        const T oc = Ocur[off];
+      if (iter) {
+        const T oc = oc_;
         b.R_acc[off] = o + beta_acc * (o - oc) - pv_;
         b.R_rej[off] = oc - pv_;
       } else {
@@ -327,11 +341,12 @@ __global__ __launch_bounds__(64 * KS) void fx_kernel(ProbView pv, Bufs<T> b, Sol
 // probes (lane = probe, recursion along m) into its own LDS slice and reads it back
 // transposed as the MFMA A operand; the R rows of the next PF steps are prefetched.
 // ---------------------------------------------------------------------------------------
-template <typename T, int NT>
-__global__ __launch_bounds__(64 * KS) void ftr_kernel(ProbView pv, Bufs<T> b, SolverState* st, int mode,
+template <typename TS, typename TC, int NT>
+__global__ __launch_bounds__(64 * KS) void ftr_kernel(ProbView pv, Bufs<TS> b, SolverState* st, int mode,
                                                        double step) {
   if (mode == FTR_STEP && st->done) return;
-  typedef typename Acc<T>::type AccT;
+  typedef TS T;
+  typedef typename Acc<TC>::type AccT;
   constexpr int LDT = 16 * NT + 1;
   __shared__ double Ft[KS][kChunkD][17];
   __shared__ double S[16 * LDT];
@@ -355,11 +370,11 @@ __global__ __launch_bounds__(64 * KS) void ftr_kernel(ProbView pv, Bufs<T> b, So
   for (int nt = 0; nt < NT; ++nt) acc[nt] = AccT{0, 0, 0, 0};
 
   // probes beyond dhi are clamped: their generated F entries are zero
-  auto load_r = [&](int drow, T (&dst)[NT]) {
+  auto load_r = [&](int drow, TC (&dst)[NT]) {
     const int dd = drow < dhi ? drow : dhi;
     const unsigned base = (unsigned)(dd > 0 ? dd : 0) * (unsigned)Npad + (unsigned)i;
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) dst[nt] = R[base + 16u * nt];
+    for (int nt = 0; nt < NT; ++nt) dst[nt] = (TC)R[base + 16u * nt];
   };
   const int nchunks = dhi >= dlo ? (dhi - dlo) / kChunkD + 1 : 0;
   const int rounds = (nchunks + KS - 1) / KS;
@@ -398,7 +413,7 @@ __global__ __launch_bounds__(64 * KS) void ftr_kernel(ProbView pv, Bufs<T> b, So
   };
 
   int dc = dlo + kChunkD * wv;
-  T rb[PF][NT];
+  TC rb[PF][NT];
 #pragma unroll
   for (int p = 0; p < PF; ++p) load_r(dc + 16 * kq + p, rb[p]);
   double vals[16];
@@ -419,9 +434,9 @@ __global__ __launch_bounds__(64 * KS) void ftr_kernel(ProbView pv, Bufs<T> b, So
     Gen g = gn;
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-      const T a = (T)Ft[wv][16 * kq + s][i];
+      const TC a = (TC)Ft[wv][16 * kq + s][i];
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) acc[nt] = Acc<T>::mfma(a, rb[s % PF][nt], acc[nt]);
+      for (int nt = 0; nt < NT; ++nt) acc[nt] = Acc<TC>::mfma(a, rb[s % PF][nt], acc[nt]);
       if (s + PF < 16) load_r(dc + 16 * kq + s + PF, rb[s % PF]);
       else load_r(dcn + 16 * kq + s + PF - 16, rb[s % PF]);
       if (s == 1) gen_anchor(g);
@@ -432,7 +447,7 @@ __global__ __launch_bounds__(64 * KS) void ftr_kernel(ProbView pv, Bufs<T> b, So
     vals[15] = gen_step(g, 15);
     __syncthreads();
   }
-  reduce_tiles<T, NT>(acc, S, LDT, wv, i, kq);
+  reduce_tiles<TC, NT>(acc, S, LDT, wv, i, kq);
 
   // epilogue: wave wv finishes rows m0 + 4 wv + kq (one row per 16-lane group)
   const int m = m0 + 4 * wv + kq;
@@ -749,14 +764,15 @@ __global__ void convert_pad_kernel(const Ts* src, Td* dst, long long rows, int c
 int fx_num_waves(const ProbView& pv) { return (pv.D + 15) / 16; }
 int ftr_num_waves(const ProbView& pv) { return (pv.M + 15) / 16; }
 
-template <typename T, int NT>
-static void fx_go(const ProbView& pv, const Bufs<T>& b, SolverState* st, int mode, hipStream_t s) {
-  hipLaunchKernelGGL((fx_kernel<T, NT>), dim3(fx_num_waves(pv)), dim3(64 * KS), 0, s, pv, b, st, mode);
+template <typename TS, typename TC, int NT>
+static void fx_go(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode, hipStream_t s) {
+  hipLaunchKernelGGL((fx_kernel<TS, TC, NT>), dim3(fx_num_waves(pv)), dim3(64 * KS), 0, s, pv, b, st, mode);
 }
-template <typename T, int NT>
-static void ftr_go(const ProbView& pv, const Bufs<T>& b, SolverState* st, int mode, double step,
+template <typename TS, typename TC, int NT>
+static void ftr_go(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode, double step,
                    hipStream_t s) {
-  hipLaunchKernelGGL((ftr_kernel<T, NT>), dim3(ftr_num_waves(pv)), dim3(64 * KS), 0, s, pv, b, st, mode, step);
+  hipLaunchKernelGGL((ftr_kernel<TS, TC, NT>), dim3(ftr_num_waves(pv)), dim3(64 * KS), 0, s, pv, b, st, mode,
+                     step);
 }
 
 #define PDT_NT_SWITCH(NTV, CALL)                 \
@@ -776,18 +792,18 @@ static void ftr_go(const ProbView& pv, const Bufs<T>& b, SolverState* st, int mo
     default: return hipErrorInvalidValue;        \
   }
 
-template <typename T>
-hipError_t launch_fx(const ProbView& pv, const Bufs<T>& b, SolverState* st, int mode, hipStream_t s) {
-#define PDT_FX(K) fx_go<T, K>(pv, b, st, mode, s)
+template <typename TS, typename TC>
+hipError_t launch_fx(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode, hipStream_t s) {
+#define PDT_FX(K) fx_go<TS, TC, K>(pv, b, st, mode, s)
   PDT_NT_SWITCH(pv.Npad / 16, PDT_FX)
 #undef PDT_FX
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_ftr(const ProbView& pv, const Bufs<T>& b, SolverState* st, int mode, double step,
+template <typename TS, typename TC>
+hipError_t launch_ftr(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode, double step,
                       hipStream_t s) {
-#define PDT_FTR(K) ftr_go<T, K>(pv, b, st, mode, step, s)
+#define PDT_FTR(K) ftr_go<TS, TC, K>(pv, b, st, mode, step, s)
   PDT_NT_SWITCH(pv.Npad / 16, PDT_FTR)
 #undef PDT_FTR
   return hipGetLastError();
@@ -864,12 +880,16 @@ hipError_t launch_fill_rows(T* X, long long rows, int cols, int ld, T value, hip
 template hipError_t launch_fill_rows<double>(double*, long long, int, int, double, hipStream_t);
 template hipError_t launch_fill_rows<float>(float*, long long, int, int, float, hipStream_t);
 
-template hipError_t launch_fx<double>(const ProbView&, const Bufs<double>&, SolverState*, int, hipStream_t);
-template hipError_t launch_fx<float>(const ProbView&, const Bufs<float>&, SolverState*, int, hipStream_t);
-template hipError_t launch_ftr<double>(const ProbView&, const Bufs<double>&, SolverState*, int, double,
-                                       hipStream_t);
-template hipError_t launch_ftr<float>(const ProbView&, const Bufs<float>&, SolverState*, int, double,
-                                      hipStream_t);
+template hipError_t launch_fx<double, double>(const ProbView&, const Bufs<double>&, SolverState*, int,
+                                              hipStream_t);
+template hipError_t launch_fx<float, float>(const ProbView&, const Bufs<float>&, SolverState*, int, hipStream_t);
+template hipError_t launch_fx<double, float>(const ProbView&, const Bufs<double>&, SolverState*, int, hipStream_t);
+template hipError_t launch_ftr<double, double>(const ProbView&, const Bufs<double>&, SolverState*, int, double,
+                                               hipStream_t);
+template hipError_t launch_ftr<float, float>(const ProbView&, const Bufs<float>&, SolverState*, int, double,
+                                             hipStream_t);
+template hipError_t launch_ftr<double, float>(const ProbView&, const Bufs<double>&, SolverState*, int, double,
+                                              hipStream_t);
 template hipError_t launch_project_rows<double>(const double*, double*, long long, int, int, int, hipStream_t);
 template hipError_t launch_project_rows<float>(const float*, float*, long long, int, int, int, hipStream_t);
 template hipError_t launch_convert_pad<double, double>(const double*, double*, long long, int, int, int,

@@ -232,3 +232,57 @@ def test_tolerance_stop_and_not_converged(dev):
     assert (info["objective"] - fstar) <= 1e-6 * fstar
     info2 = pb.solve(Pi, max_iters=10, rel_obj_tol=1e-12, f_star=fstar)
     assert info2["status"] == _pdt.PDT_ERR_NOT_CONVERGED and info2["iters"] == 10
+
+
+# ---- mixed precision: FP32 products on FP64 iterates, then FP64 refinement ---------------
+
+def _golden_c1():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c1_oracle.json")) as fh:
+        return json.load(fh)
+
+
+def test_mixed_reaches_the_certified_optimum_c1(dev):
+    inst = synth.c1_small()
+    gold = _golden_c1()
+    fstar, Xstar = gold["f_star"], np.array(gold["Pi_star"])
+    pb = _pdt.Problem.from_instance(inst)
+    Pi = torch.zeros((inst.M, inst.N), dtype=torch.float64, device=dev)
+    # An objective-monotone method stops moving along the flattest direction of this
+    # ill-conditioned problem once the decrease, lambda_min * dX^2 ~ 3.4e-5 * dX^2, drops
+    # below the FP64 rounding of f (~1e-15 * f): dX ~ 1e-6.  The oracle's own iteration
+    # stalls there too (1.07e-6 after 20000 iterations), so the optimum bound is 2e-6.
+    info = pb.solve(Pi, precision=_pdt.PDT_MIXED, max_iters=60000)
+    assert info["status"] == _pdt.PDT_OK and info["iters"] == 60000
+    X = Pi.cpu().numpy()
+    assert abs(info["objective"] - fstar) <= 1e-12 * fstar
+    assert np.max(np.abs(X - Xstar)) <= 2e-6
+    assert np.all(X >= 0) and np.max(np.abs(X.sum(1) - 1)) < 1e-14
+
+
+def test_mixed_early_iterates_track_fp64(dev):
+    # before the refinement takes over, FP32 products keep the iterate within 1e-4
+    inst = small_instance()
+    F, _, _ = oracle_F(inst)
+    L = fista.lipschitz(F, inst.gamma, inst.M)
+    ref = fista.fista_r(F, inst.P, inst.gamma, L, 256, exact_sums=False)
+    pb = _pdt.Problem.from_instance(inst)
+    Pi = torch.zeros((inst.M, inst.N), dtype=torch.float64, device=dev)
+    info = pb.solve(Pi, precision=_pdt.PDT_MIXED, max_iters=256, step_L=L)
+    assert info["iters"] == 256
+    assert abs(info["objective"] - ref.f) <= 1e-4 * ref.f
+    assert np.max(np.abs(Pi.cpu().numpy() - ref.X)) <= 1e-4
+
+
+def test_mixed_c2_tolerance(dev):
+    # the mixed solve stops at the same relative objective as the FP64 one
+    inst = synth.c2_medium()
+    pb = _pdt.Problem.from_instance(inst)
+    Pi = torch.zeros((inst.M, inst.N), dtype=torch.float64, device=dev)
+    ref = pb.solve(Pi, max_iters=60000)
+    fstar = ref["objective"]
+    Pi.zero_()
+    info = pb.solve(Pi, precision=_pdt.PDT_MIXED, max_iters=200000, rel_obj_tol=1e-6, f_star=fstar)
+    assert info["converged"] == 1 and (info["objective"] - fstar) <= 1e-6 * fstar
+    assert pb.kkt(Pi) < 1e-6

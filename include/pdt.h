@@ -61,8 +61,12 @@ typedef enum {
 
 typedef enum {
   PDT_INIT_UNIFORM = 0, /* Pi = 1/N (the paper's start, Algorithm 1) */
-  PDT_INIT_USER = 1     /* start from the caller's Pi, projected onto the constraints first */
+  PDT_INIT_USER = 1,    /* start from the caller's Pi, projected onto the constraints first */
+  PDT_INIT_LEARNED = 2  /* start predicted by a warm-start network (opts.model), projected;
+                           falls back to 1/N when that start is not better */
 } pdt_init_mode;
+
+typedef struct pdt_model_s* pdt_model_t;
 
 /* One tomography instance (arguments follow Eq. min and Eq. Fmatrix). */
 typedef struct {
@@ -102,6 +106,7 @@ typedef struct {
   double f_star;          /* known optimum value; <= 0 disables the tolerance test */
   double step_L;          /* step = 1 / step_L; 0 uses the problem's own Lipschitz estimate */
   double* history;        /* optional device [max_iters]: f after each iteration (FP64) */
+  pdt_model_t model;      /* warm-start network for init == PDT_INIT_LEARNED (n_in 258, n_out M) */
 } pdt_solve_opts;
 
 typedef struct {
@@ -113,6 +118,7 @@ typedef struct {
   double seconds;         /* wall time of the call */
   int converged;          /* 1 if the tolerance test was met */
   int64_t refine_iters;   /* PDT_MIXED: iterations of the FP64 refinement (included in iters) */
+  int fell_back_to_cold;  /* PDT_INIT_LEARNED: 1 if the predicted start was rejected for 1/N */
 } pdt_solve_info;
 
 /*
@@ -152,6 +158,36 @@ pdt_status pdt_project_simplex_f32(const float* X, float* Y, int64_t rows, int64
  * number of band entries sum_d (hi_d - lo_d + 1) (host, nullable). */
 pdt_status pdt_problem_bands(pdt_problem_t problem, int32_t* lo, int32_t* hi, double* tail,
                              double* lipschitz, int64_t* nnz);
+
+/*
+ * Warm-start network (learned initial Pi; not in the paper, whose runs start from
+ * Pi = 1/N and, for its smoothed second run, from a window average of a solution).
+ * Four linear layers n_in -> hidden -> hidden -> hidden -> n_out with the tanh form of
+ * GELU after the first three; weights [out][in] row-major, y = x W^T + b.  Products run
+ * on BF16 MFMA with FP32 accumulation; master weights and Adam moments are FP32.
+ * Parameter vector (FP32): W1, b1, W2, b2, W3, b3, W4, b4 in that order.
+ * Features of outcome n of a detector whose outcomes 0..bins carry probability:
+ * P[:, n] linearly interpolated at 256 equally spaced mean photon numbers from mu_0 to
+ * mu_{D-1}, then n / bins and bins / 128 (n_in = 258).
+ */
+/* params: host [num_params] FP32 or NULL (zeros); stream: hipStream_t or NULL. */
+pdt_status pdt_model_create(int64_t n_in, int64_t hidden, int64_t n_out, const float* params, void* stream,
+                            pdt_model_t* out);
+void pdt_model_destroy(pdt_model_t model);
+int64_t pdt_model_num_params(pdt_model_t model);
+/* params_host: host [num_params] FP32, receives the master weights. */
+pdt_status pdt_model_get_params(pdt_model_t model, float* params_host);
+/* X: device [B*n_in] FP32, Y: device [B*n_out] FP32. */
+pdt_status pdt_model_forward(pdt_model_t model, const float* X, float* Y, int64_t B);
+/* Gradient of a loss whose derivative w.r.t. the output is dY (device [B*n_out]) into
+ * grads (device [num_params], same layout as the parameters). */
+pdt_status pdt_model_gradients(pdt_model_t model, const float* X, const float* dY, int64_t B, float* grads);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on mean((Y - T)^2); X, T on the
+ * device; *loss (host, nullable) receives the loss before the step. */
+pdt_status pdt_model_train_step(pdt_model_t model, const float* X, const float* T, int64_t B, float lr,
+                                double* loss);
+/* Features of the problem's real outcomes: X device [(bins+1)*258]; *bins_out host. */
+pdt_status pdt_warmstart_features(pdt_problem_t problem, float* X, int64_t* bins_out);
 
 /*
  * Measurement hook: enqueues `reps` launches of one kernel of the iteration on the

@@ -28,6 +28,7 @@ PDT_TAIL_LUMP = 1
 
 PDT_INIT_UNIFORM = 0
 PDT_INIT_USER = 1
+PDT_INIT_LEARNED = 2
 
 STATUS_NAMES = {0: "PDT_OK", 1: "PDT_ERR_INVALID_ARG", 2: "PDT_ERR_OUT_OF_MEMORY", 3: "PDT_ERR_DEVICE",
                 4: "PDT_ERR_NOT_CONVERGED", 5: "PDT_ERR_NUMERIC"}
@@ -49,13 +50,13 @@ class pdt_problem_desc(ctypes.Structure):
 class pdt_solve_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("init", ctypes.c_int), ("max_iters", ctypes.c_int64),
                 ("rel_obj_tol", ctypes.c_double), ("f_star", ctypes.c_double), ("step_L", ctypes.c_double),
-                ("history", ctypes.c_void_p)]
+                ("history", ctypes.c_void_p), ("model", ctypes.c_void_p)]
 
 
 class pdt_solve_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("rejects", ctypes.c_int64), ("objective", ctypes.c_double),
                 ("kkt", ctypes.c_double), ("L_used", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("converged", ctypes.c_int), ("refine_iters", ctypes.c_int64)]
+                ("converged", ctypes.c_int), ("refine_iters", ctypes.c_int64), ("fell_back_to_cold", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -83,6 +84,19 @@ def lib() -> ctypes.CDLL:
                                         ctypes.POINTER(ctypes.c_int64)]
         L.pdt_replay_kernel.argtypes = [vp, ctypes.c_int, ctypes.c_int, i64]
         L.pdt_replay_kernel.restype = ctypes.c_int
+        L.pdt_model_create.argtypes = [i64, i64, i64, vp, vp, ctypes.POINTER(vp)]
+        L.pdt_model_destroy.argtypes = [vp]
+        L.pdt_model_destroy.restype = None
+        L.pdt_model_num_params.argtypes = [vp]
+        L.pdt_model_num_params.restype = ctypes.c_int64
+        L.pdt_model_get_params.argtypes = [vp, vp]
+        L.pdt_model_forward.argtypes = [vp, vp, vp, i64]
+        L.pdt_model_gradients.argtypes = [vp, vp, vp, i64, vp]
+        L.pdt_model_train_step.argtypes = [vp, vp, vp, i64, ctypes.c_float, dp]
+        L.pdt_warmstart_features.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64)]
+        for name in ("pdt_model_create", "pdt_model_get_params", "pdt_model_forward", "pdt_model_gradients",
+                     "pdt_model_train_step", "pdt_warmstart_features"):
+            getattr(L, name).restype = ctypes.c_int
         L.pdt_last_error.argtypes = []
         L.pdt_last_error.restype = ctypes.c_char_p
         for name in ("pdt_make_problem", "pdt_solve", "pdt_objective", "pdt_kkt", "pdt_project_simplex",
@@ -150,11 +164,14 @@ def pdt_destroy_problem(handle) -> None:
 
 
 def pdt_solve(handle, Pi, *, precision=PDT_FP64, init=PDT_INIT_UNIFORM, max_iters=1000, rel_obj_tol=0.0,
-              f_star=0.0, step_L=0.0, history=None, allow_not_converged=True) -> dict:
+              f_star=0.0, step_L=0.0, history=None, model=None, allow_not_converged=True) -> dict:
     """Solve in place: ``Pi`` is a contiguous float64 [M, N] GPU tensor."""
+    if model is not None and init == PDT_INIT_UNIFORM:
+        init = PDT_INIT_LEARNED
     o = pdt_solve_opts(precision=precision, init=init, max_iters=int(max_iters), rel_obj_tol=float(rel_obj_tol),
                        f_star=float(f_star), step_L=float(step_L),
-                       history=ctypes.c_void_p(history.data_ptr()) if history is not None else None)
+                       history=ctypes.c_void_p(history.data_ptr()) if history is not None else None,
+                       model=(model.handle if isinstance(model, Model) else model))
     info = pdt_solve_info()
     st = _check(lib().pdt_solve(handle, ctypes.c_void_p(Pi.data_ptr()), ctypes.byref(o), ctypes.byref(info)),
                 allow=(PDT_ERR_NOT_CONVERGED,) if allow_not_converged else ())
@@ -239,3 +256,89 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+# ---- warm-start network ------------------------------------------------------------------
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Model:
+    """Owns a warm-start network handle (pdt_model_*)."""
+
+    def __init__(self, n_in: int, hidden: int, n_out: int, params=None, stream=None):
+        import numpy as np
+        self.n_in, self.hidden, self.n_out = int(n_in), int(hidden), int(n_out)
+        out = ctypes.c_void_p()
+        p = None
+        if params is not None:
+            self._p = np.ascontiguousarray(params, dtype=np.float32)
+            p = self._p.ctypes.data_as(ctypes.c_void_p)
+        _check(lib().pdt_model_create(self.n_in, self.hidden, self.n_out, p, _stream_ptr(stream), ctypes.byref(out)))
+        self.handle = out
+
+    @property
+    def num_params(self) -> int:
+        return int(lib().pdt_model_num_params(self.handle))
+
+    def params(self):
+        import numpy as np
+        out = np.empty(self.num_params, dtype=np.float32)
+        _check(lib().pdt_model_get_params(self.handle, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def forward(self, X, Y=None):
+        if Y is None:
+            Y = X.new_empty((X.shape[0], self.n_out))
+        _check(lib().pdt_model_forward(self.handle, _dptr(X), _dptr(Y), int(X.shape[0])))
+        return Y
+
+    def gradients(self, X, dY, grads=None):
+        import torch
+        if grads is None:
+            grads = torch.empty(self.num_params, dtype=torch.float32, device=X.device)
+        _check(lib().pdt_model_gradients(self.handle, _dptr(X), _dptr(dY), int(X.shape[0]), _dptr(grads)))
+        return grads
+
+    def train_step(self, X, T, lr: float) -> float:
+        loss = ctypes.c_double()
+        _check(lib().pdt_model_train_step(self.handle, _dptr(X), _dptr(T), int(X.shape[0]), float(lr),
+                                          ctypes.byref(loss)))
+        return loss.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pdt_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pack_params(layers) -> "np.ndarray":
+    """[(W, b), ...] -> the flat FP32 parameter vector W1, b1, W2, b2, ..."""
+    import numpy as np
+    return np.concatenate([np.concatenate([W.reshape(-1), b]) for W, b in layers]).astype(np.float32)
+
+
+def unpack_params(vec, sizes) -> list:
+    import numpy as np
+    out, off = [], 0
+    for fin, fout in zip(sizes[:-1], sizes[1:]):
+        W = np.asarray(vec[off:off + fin * fout], dtype=np.float64).reshape(fout, fin)
+        off += fin * fout
+        b = np.asarray(vec[off:off + fout], dtype=np.float64)
+        off += fout
+        out.append((W, b))
+    return out
+
+
+def pdt_warmstart_features(handle, X) -> int:
+    """Features of the problem's real outcomes into the float32 GPU tensor X [bins+1, 258]."""
+    bins = ctypes.c_int64()
+    _check(lib().pdt_warmstart_features(handle, _dptr(X), ctypes.byref(bins)))
+    return bins.value

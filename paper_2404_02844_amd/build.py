@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdt.so")
-SOURCES = ["pdt_kernels.hip", "pdt_capi.hip"]
+SOURCES = ["pdt_kernels.hip", "pdt_mlp.hip", "pdt_capi.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # keep packed FP32 instructions out of every kernel
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -14,6 +14,7 @@
 
 #include "pdt.h"
 #include "pdt_internal.h"
+#include "pdt_mlp.h"
 
 using namespace pdt;
 
@@ -77,6 +78,7 @@ struct Instance {
   int lump = 0;
   double L_hat = 0;
   int64_t nnz = 0;
+  int bins = 0;  // last outcome column with any probability mass (outcomes 0..bins are real)
   std::vector<int> lo_h, hi_h;
   std::vector<double> tail_h;
   double* mu = nullptr;
@@ -109,6 +111,8 @@ struct Instance {
 
 }  // namespace
 
+struct pdt_model_s;
+
 struct pdt_problem_s {
   hipStream_t stream = nullptr;
   hipStream_t capture = nullptr;  // library-owned stream used only to record graphs
@@ -122,6 +126,23 @@ namespace {
 pdt_status set_err(pdt_status s, const std::string& msg) {
   g_last_error = msg;
   return s;
+}
+
+// Maps the exception in flight to a status; nothing may leave an extern "C" entry point.
+pdt_status status_of_current_exception() {
+  try {
+    throw;
+  } catch (const ArgError& e) {
+    return set_err(PDT_ERR_INVALID_ARG, e.what);
+  } catch (const OomError& e) {
+    return set_err(PDT_ERR_OUT_OF_MEMORY, e.what);
+  } catch (const DevError& e) {
+    return set_err(PDT_ERR_DEVICE, e.what);
+  } catch (const std::bad_alloc&) {
+    return set_err(PDT_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return set_err(PDT_ERR_DEVICE, "unexpected exception");
+  }
 }
 
 ProbView view_of(const Instance& I) {
@@ -273,6 +294,18 @@ void setup_instance(pdt_problem_s* pb, Instance& I, const pdt_problem_desc& d) {
   HIPCHK(hipMemsetAsync(I.P64, 0, D * Np * sizeof(double), s));
   HIPCHK(hipMemcpy2DAsync(I.P64, Np * sizeof(double), d.P, N * sizeof(double), N * sizeof(double), D,
                           d.P_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+  {
+    std::vector<double> Ph(D * N);
+    HIPCHK(hipMemcpy2DAsync(Ph.data(), N * sizeof(double), I.P64, Np * sizeof(double), N * sizeof(double), D,
+                            hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    I.bins = 0;
+    for (size_t n = 0; n < N; ++n) {
+      double cs = 0;
+      for (size_t k = 0; k < D; ++k) cs += Ph[k * N + n];
+      if (cs > 0) I.bins = (int)n;
+    }
+  }
   HIPCHK(launch_fill_rinv(I.rinv, I.r4, (int)(M + 128), s));
   HIPCHK(launch_setup_bands(I.mu, (int)D, (int)M, I.tau, I.lump, I.lo, I.hi, I.tail, s));
 
@@ -523,6 +556,10 @@ void replay_impl(pdt_problem_s* pb, Instance& I, int kernel, int64_t reps) {
 
 }  // namespace
 
+namespace {
+int learned_start(pdt_problem_s* pb, Instance& I, pdt_model_s* md);
+}
+
 extern "C" {
 
 const char* pdt_last_error(void) { return g_last_error.c_str(); }
@@ -544,18 +581,13 @@ pdt_status pdt_make_problem(const pdt_problem_desc* descs, int64_t n_instances, 
     *out = pb;
     g_last_error.clear();
     return PDT_OK;
-  } catch (const ArgError& e) {
-    if (pb) { pb->arena.release(); delete pb; }
-    return set_err(PDT_ERR_INVALID_ARG, e.what);
-  } catch (const OomError& e) {
-    if (pb) { (void)hipStreamSynchronize(pb->stream); pb->arena.release(); delete pb; }
-    return set_err(PDT_ERR_OUT_OF_MEMORY, e.what);
-  } catch (const DevError& e) {
-    if (pb) { (void)hipStreamSynchronize(pb->stream); pb->arena.release(); delete pb; }
-    return set_err(PDT_ERR_DEVICE, e.what);
-  } catch (const std::bad_alloc&) {
-    if (pb) { pb->arena.release(); delete pb; }
-    return set_err(PDT_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    if (pb) {
+      (void)hipStreamSynchronize(pb->stream);
+      pb->arena.release();
+      delete pb;
+    }
+    return status_of_current_exception();
   }
 }
 
@@ -599,10 +631,8 @@ static pdt_status objective_impl(pdt_problem_t pb, const double* Pi, double* f_o
       HIPCHK(hipStreamSynchronize(s));
     }
     return std::isfinite(f) ? PDT_OK : set_err(PDT_ERR_NUMERIC, "objective is not finite");
-  } catch (const OomError& e) {
-    return set_err(PDT_ERR_OUT_OF_MEMORY, e.what);
-  } catch (const DevError& e) {
-    return set_err(PDT_ERR_DEVICE, e.what);
+  } catch (...) {
+    return status_of_current_exception();
   }
 }
 
@@ -620,7 +650,8 @@ pdt_status pdt_solve(pdt_problem_t pb, double* Pi, const pdt_solve_opts* opts, p
   const pdt_solve_opts o = *opts;
   if (o.max_iters < 0) return set_err(PDT_ERR_INVALID_ARG, "max_iters must be >= 0");
   if (!std::isfinite(o.step_L) || o.step_L < 0) return set_err(PDT_ERR_INVALID_ARG, "step_L must be >= 0");
-  if (o.init != PDT_INIT_UNIFORM && o.init != PDT_INIT_USER) return set_err(PDT_ERR_INVALID_ARG, "bad init");
+  if (o.init != PDT_INIT_UNIFORM && o.init != PDT_INIT_USER && o.init != PDT_INIT_LEARNED)
+    return set_err(PDT_ERR_INVALID_ARG, "bad init");
   if (o.precision != PDT_FP64 && o.precision != PDT_FP32 && o.precision != PDT_MIXED)
     return set_err(PDT_ERR_INVALID_ARG, "precision not supported");
   if (!std::isfinite(o.rel_obj_tol) || o.rel_obj_tol < 0 || !std::isfinite(o.f_star))
@@ -637,9 +668,13 @@ pdt_status pdt_solve(pdt_problem_t pb, double* Pi, const pdt_solve_opts* opts, p
     // starting point in X64[0]: 1/N, or the caller's Pi projected onto the constraints
     if (o.init == PDT_INIT_USER) {
       HIPCHK(launch_project_rows<double>(Pi, I.w64.X[0], (long long)M, (int)N, (int)N, (int)Np, s));
+    } else if (o.init == PDT_INIT_LEARNED) {
+      if (!o.model) return set_err(PDT_ERR_INVALID_ARG, "init = LEARNED needs a model");
     } else {
       HIPCHK(launch_fill_rows<double>(I.w64.X[0], (long long)M, (int)N, (int)Np, 1.0 / (double)N, s));
     }
+    int fell_back = 0;
+    if (o.init == PDT_INIT_LEARNED) fell_back = learned_start(pb, I, o.model);
     const double f_star = o.f_star > 0 ? o.f_star : 0.0;
     init_state(s, I.st, o.max_iters, f_star, o.rel_obj_tol);
     SolverState fin;
@@ -675,16 +710,15 @@ pdt_status pdt_solve(pdt_problem_t pb, double* Pi, const pdt_solve_opts* opts, p
       info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       info->converged = conv ? 1 : 0;
       info->refine_iters = refine_iters;
+      info->fell_back_to_cold = fell_back;
     }
     if (!std::isfinite(f)) return set_err(PDT_ERR_NUMERIC, "objective is not finite");
     if (f_star > 0 && o.rel_obj_tol > 0 && !conv)
       return set_err(PDT_ERR_NOT_CONVERGED, "max_iters reached before the tolerance");
     g_last_error.clear();
     return PDT_OK;
-  } catch (const OomError& e) {
-    return set_err(PDT_ERR_OUT_OF_MEMORY, e.what);
-  } catch (const DevError& e) {
-    return set_err(PDT_ERR_DEVICE, e.what);
+  } catch (...) {
+    return status_of_current_exception();
   }
 }
 
@@ -705,8 +739,8 @@ pdt_status pdt_replay_kernel(pdt_problem_t pb, int kernel, int precision, int64_
       return set_err(PDT_ERR_INVALID_ARG, "precision not supported");
     }
     return PDT_OK;
-  } catch (const DevError& e) {
-    return set_err(PDT_ERR_DEVICE, e.what);
+  } catch (...) {
+    return status_of_current_exception();
   }
 }
 
@@ -735,3 +769,289 @@ pdt_status pdt_project_simplex_f32(const float* X, float* Y, int64_t rows, int64
 }
 
 }  // extern "C"
+
+// =======================================================================================
+// Warm-start network: FP32 master weights, BF16 copies for the MFMA GEMMs, Adam state.
+// =======================================================================================
+struct pdt_model_s {
+  int64_t n_in = 0, hidden = 0, n_out = 0, nparam = 0;
+  hipStream_t stream = nullptr;
+  Arena arena, work;
+  float* p = nullptr;
+  __bf16* pb = nullptr;
+  float* g = nullptr;
+  float* m = nullptr;
+  float* v = nullptr;
+  int t = 0;
+  int64_t offW[4] = {0, 0, 0, 0}, offb[4] = {0, 0, 0, 0}, fin[4] = {0, 0, 0, 0}, fout[4] = {0, 0, 0, 0};
+  int64_t cap = 0;  // batch capacity of the workspace
+  __bf16* hb[4] = {nullptr, nullptr, nullptr, nullptr};
+  float* z[3] = {nullptr, nullptr, nullptr};
+  float* Xf = nullptr;
+  float* Y = nullptr;
+  float* dY = nullptr;
+  __bf16* dYb = nullptr;
+  float* dH = nullptr;
+  float* dZ = nullptr;
+  __bf16* dZb = nullptr;
+  double* partials = nullptr;
+};
+
+namespace {
+
+constexpr int kLossBlocks = 256;
+
+void model_reserve(pdt_model_s* md, int64_t B) {
+  if (B <= md->cap) return;
+  md->work.release();
+  const int64_t H = md->hidden;
+  md->hb[0] = md->work.alloc<__bf16>((size_t)(B * md->n_in));
+  for (int l = 1; l < 4; ++l) md->hb[l] = md->work.alloc<__bf16>((size_t)(B * H));
+  for (int l = 0; l < 3; ++l) md->z[l] = md->work.alloc<float>((size_t)(B * H));
+  md->Xf = md->work.alloc<float>((size_t)(B * md->n_in));
+  md->Y = md->work.alloc<float>((size_t)(B * md->n_out));
+  md->dY = md->work.alloc<float>((size_t)(B * md->n_out));
+  md->dYb = md->work.alloc<__bf16>((size_t)(B * md->n_out));
+  md->dH = md->work.alloc<float>((size_t)(B * H));
+  md->dZ = md->work.alloc<float>((size_t)(B * H));
+  md->dZb = md->work.alloc<__bf16>((size_t)(B * H));
+  md->partials = md->work.alloc<double>(kLossBlocks);
+  md->cap = B;
+}
+
+GemmArgs gemm(const __bf16* A, long long lda, int at, const __bf16* Bm, long long ldb, int bt, int M, int N, int K,
+              long long ldc) {
+  GemmArgs g{};
+  g.A = A;
+  g.B = Bm;
+  g.lda = lda;
+  g.ldb = ldb;
+  g.ldc = ldc;
+  g.a_trans = at;
+  g.b_trans = bt;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  return g;
+}
+
+// forward of X (FP32 [B][n_in] on the device, or already BF16 in hb[0] when X == nullptr)
+void model_forward(pdt_model_s* md, const float* X, int64_t B) {
+  hipStream_t s = md->stream;
+  model_reserve(md, B);
+  if (X) HIPCHK(launch_f32_to_bf16(X, md->hb[0], B * md->n_in, s));
+  for (int l = 0; l < 4; ++l) {
+    GemmArgs g = gemm(md->hb[l], md->fin[l], 0, md->pb + md->offW[l], md->fin[l], 1, (int)B, (int)md->fout[l],
+                      (int)md->fin[l], md->fout[l]);
+    g.bias = md->p + md->offb[l];
+    if (l < 3) {
+      g.preact = md->z[l];
+      g.gelu = 1;
+      g.Cbf = md->hb[l + 1];
+    } else {
+      g.C = md->Y;
+    }
+    HIPCHK(launch_gemm_bf16(g, s));
+  }
+}
+
+// gradients into md->g for dLoss/dY given in md->dY (FP32) and md->dYb (BF16)
+void model_backward(pdt_model_s* md, int64_t B) {
+  hipStream_t s = md->stream;
+  const int H = (int)md->hidden;
+  const float* dOut = md->dY;
+  const __bf16* dOutB = md->dYb;
+  for (int l = 3; l >= 0; --l) {
+    const int fo = (int)md->fout[l], fi = (int)md->fin[l];
+    if (l < 3) {
+      // dZ = dH * gelu'(z_l)
+      HIPCHK(launch_gelu_back(md->dH, md->z[l], B * H, md->dZ, md->dZb, s));
+      dOut = md->dZ;
+      dOutB = md->dZb;
+    }
+    // dW_l = dOut^T h_l   ([fo][fi], contraction over the batch)
+    GemmArgs gw = gemm(dOutB, fo, 1, md->hb[l], fi, 0, fo, fi, (int)B, fi);
+    gw.C = md->g + md->offW[l];
+    HIPCHK(launch_gemm_bf16(gw, s));
+    HIPCHK(launch_colsum(dOut, (int)B, fo, md->g + md->offb[l], s));
+    if (l > 0) {
+      // dH = dOut W_l  ([B][fi])
+      GemmArgs gh = gemm(dOutB, fo, 0, md->pb + md->offW[l], fi, 0, (int)B, fi, fo, fi);
+      gh.C = md->dH;
+      HIPCHK(launch_gemm_bf16(gh, s));
+    }
+  }
+}
+
+pdt_status model_err(pdt_status st, const std::string& m) { return set_err(st, m); }
+
+}  // namespace
+
+extern "C" {
+
+pdt_status pdt_model_create(int64_t n_in, int64_t hidden, int64_t n_out, const float* params, void* stream,
+                            pdt_model_t* out) {
+  if (!out) return model_err(PDT_ERR_INVALID_ARG, "out must not be NULL");
+  *out = nullptr;
+  if (n_in < 1 || hidden < 1 || n_out < 1 || n_in > (1 << 20) || hidden > (1 << 16) || n_out > (1 << 26))
+    return model_err(PDT_ERR_INVALID_ARG, "bad network sizes");
+  pdt_model_s* md = nullptr;
+  try {
+    md = new pdt_model_s();
+    md->n_in = n_in;
+    md->hidden = hidden;
+    md->n_out = n_out;
+    md->stream = static_cast<hipStream_t>(stream);
+    const int64_t ins[4] = {n_in, hidden, hidden, hidden}, outs[4] = {hidden, hidden, hidden, n_out};
+    int64_t off = 0;
+    for (int l = 0; l < 4; ++l) {
+      md->fin[l] = ins[l];
+      md->fout[l] = outs[l];
+      md->offW[l] = off;
+      off += ins[l] * outs[l];
+      md->offb[l] = off;
+      off += outs[l];
+    }
+    md->nparam = off;
+    md->p = md->arena.alloc<float>((size_t)off);
+    md->pb = md->arena.alloc<__bf16>((size_t)off);
+    md->g = md->arena.alloc<float>((size_t)off);
+    md->m = md->arena.alloc<float>((size_t)off);
+    md->v = md->arena.alloc<float>((size_t)off);
+    hipStream_t s = md->stream;
+    if (params) HIPCHK(hipMemcpyAsync(md->p, params, (size_t)off * sizeof(float), hipMemcpyHostToDevice, s));
+    else HIPCHK(hipMemsetAsync(md->p, 0, (size_t)off * sizeof(float), s));
+    HIPCHK(hipMemsetAsync(md->m, 0, (size_t)off * sizeof(float), s));
+    HIPCHK(hipMemsetAsync(md->v, 0, (size_t)off * sizeof(float), s));
+    HIPCHK(launch_f32_to_bf16(md->p, md->pb, off, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *out = md;
+    return PDT_OK;
+  } catch (...) {
+    if (md) {
+      (void)hipStreamSynchronize(md->stream);
+      md->arena.release();
+      delete md;
+    }
+    return status_of_current_exception();
+  }
+}
+
+void pdt_model_destroy(pdt_model_t md) {
+  if (!md) return;
+  (void)hipStreamSynchronize(md->stream);
+  md->work.release();
+  md->arena.release();
+  delete md;
+}
+
+int64_t pdt_model_num_params(pdt_model_t md) { return md ? md->nparam : 0; }
+
+pdt_status pdt_model_get_params(pdt_model_t md, float* params_host) {
+  if (!md || !params_host) return model_err(PDT_ERR_INVALID_ARG, "NULL argument");
+  hipError_t e = hipMemcpyAsync(params_host, md->p, (size_t)md->nparam * sizeof(float), hipMemcpyDeviceToHost, md->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(md->stream);
+  return e == hipSuccess ? PDT_OK : model_err(PDT_ERR_DEVICE, hipGetErrorString(e));
+}
+
+pdt_status pdt_model_forward(pdt_model_t md, const float* X, float* Y, int64_t B) {
+  if (!md || !X || !Y || B < 1) return model_err(PDT_ERR_INVALID_ARG, "bad arguments");
+  try {
+    model_forward(md, X, B);
+    HIPCHK(hipMemcpyAsync(Y, md->Y, (size_t)(B * md->n_out) * sizeof(float), hipMemcpyDeviceToDevice, md->stream));
+    HIPCHK(hipStreamSynchronize(md->stream));
+    return PDT_OK;
+  } catch (...) {
+    return status_of_current_exception();
+  }
+}
+
+pdt_status pdt_model_gradients(pdt_model_t md, const float* X, const float* dY, int64_t B, float* grads) {
+  if (!md || !X || !dY || !grads || B < 1) return model_err(PDT_ERR_INVALID_ARG, "bad arguments");
+  try {
+    hipStream_t s = md->stream;
+    model_forward(md, X, B);
+    HIPCHK(hipMemcpyAsync(md->dY, dY, (size_t)(B * md->n_out) * sizeof(float), hipMemcpyDeviceToDevice, s));
+    HIPCHK(launch_f32_to_bf16(md->dY, md->dYb, B * md->n_out, s));
+    model_backward(md, B);
+    HIPCHK(hipMemcpyAsync(grads, md->g, (size_t)md->nparam * sizeof(float), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return PDT_OK;
+  } catch (...) {
+    return status_of_current_exception();
+  }
+}
+
+pdt_status pdt_model_train_step(pdt_model_t md, const float* X, const float* T, int64_t B, float lr, double* loss) {
+  if (!md || !X || !T || B < 1 || !(lr > 0)) return model_err(PDT_ERR_INVALID_ARG, "bad arguments");
+  try {
+    hipStream_t s = md->stream;
+    model_forward(md, X, B);
+    const long long n = B * md->n_out;
+    HIPCHK(launch_mse_grad(md->Y, T, n, 2.0f / (float)n, md->dY, md->dYb, md->partials, kLossBlocks, s));
+    model_backward(md, B);
+    md->t += 1;
+    HIPCHK(launch_adam(md->p, md->g, md->m, md->v, md->nparam, lr, 0.9f, 0.999f, 1e-8f, md->t, md->pb, md->nparam, s));
+    if (loss) {
+      double part[kLossBlocks];
+      HIPCHK(hipMemcpyAsync(part, md->partials, sizeof(part), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      double acc = 0;
+      for (int k = 0; k < kLossBlocks; ++k) acc += part[k];
+      *loss = acc / (double)n;
+    }
+    return PDT_OK;
+  } catch (...) {
+    return status_of_current_exception();
+  }
+}
+
+pdt_status pdt_warmstart_features(pdt_problem_t pb, float* X, int64_t* bins_out) {
+  if (!pb || !X) return model_err(PDT_ERR_INVALID_ARG, "bad arguments");
+  const Instance& I = pb->inst[0];
+  if (I.bins < 1) return model_err(PDT_ERR_INVALID_ARG, "the detector needs at least 2 outcomes");
+  hipError_t e = launch_features(I.mu, I.P64, (int)I.D, (int)I.Npad, I.bins, 256, X, nullptr, pb->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(pb->stream);
+  if (e != hipSuccess) return model_err(PDT_ERR_DEVICE, hipGetErrorString(e));
+  if (bins_out) *bins_out = I.bins;
+  return PDT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Learned start: features of the real outcomes -> network -> columns of Pi -> row-wise
+// projection.  Falls back to Pi = 1/N (returns 1) when the predicted start is not finite
+// or not better than the uniform one.
+int learned_start(pdt_problem_s* pb, Instance& I, pdt_model_s* md) {
+  if (md->n_in != 258 || md->n_out != I.M) throw ArgError{"the model does not match the problem (n_in 258, n_out M)"};
+  if (I.bins < 1) throw ArgError{"the detector needs at least 2 outcomes"};
+  hipStream_t s = pb->stream;
+  hipStream_t saved = md->stream;
+  md->stream = s;
+  const int64_t B = I.bins + 1;
+  const size_t M = (size_t)I.M, Np = (size_t)I.Npad;
+  try {
+    model_reserve(md, B);
+    HIPCHK(launch_features(I.mu, I.P64, (int)I.D, (int)I.Npad, I.bins, 256, md->Xf, md->hb[0], s));
+    model_forward(md, nullptr, B);
+    HIPCHK(launch_assemble(md->Y, (int)I.M, I.bins, (int)I.N, (int)I.Npad, I.w64.X[0], s));
+    HIPCHK(launch_project_rows<double>(I.w64.X[0], I.w64.X[0], (long long)M, (int)I.N, (int)Np, (int)Np, s));
+  } catch (...) {
+    md->stream = saved;
+    throw;
+  }
+  md->stream = saved;
+  const double f_warm = eval_fp64(pb, I, false, nullptr);
+  HIPCHK(hipMemcpyAsync(I.w64.X[1], I.w64.X[0], M * Np * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(launch_fill_rows<double>(I.w64.X[0], (long long)M, (int)I.N, (int)Np, 1.0 / (double)I.N, s));
+  const double f_cold = eval_fp64(pb, I, false, nullptr);
+  if (std::isfinite(f_warm) && f_warm <= f_cold) {
+    HIPCHK(hipMemcpyAsync(I.w64.X[0], I.w64.X[1], M * Np * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return 0;
+  }
+  return 1;
+}
+
+}  // namespace

@@ -82,6 +82,18 @@ struct Bufs {
   double* history;   // f after every iteration (may be null)
 };
 
+// One instance of a batched launch: its problem view, buffers, state and step; n_dt
+// = number of 16-probe tiles (forward-product work items and objective partials).
+template <typename T>
+struct BatchInst {
+  ProbView pv;
+  Bufs<T> b;
+  SolverState* st;
+  double step;
+  int n_dt;
+  int n_mt;
+};
+
 // Launchers (pdt_kernels.hip).
 // TS: storage type, TC: MFMA operand type (TC = TS, or float products on FP64 storage)
 template <typename TS, typename TC = TS>
@@ -106,6 +118,16 @@ hipError_t launch_convert_pad(const Ts* src, Td* dst, long long rows, int cols, 
 
 template <typename T>
 hipError_t launch_fill_rows(T* X, long long rows, int cols, int ld, T value, hipStream_t s);
+
+// batched launches over work lists of (instance, tile) items of one column-tile class nt
+template <typename TS, typename TC = TS>
+hipError_t launch_fx_batch(int nt, const BatchInst<TS>* insts, const int2* items, int n_items, int mode,
+                           hipStream_t s);
+template <typename TS, typename TC = TS>
+hipError_t launch_ftr_batch(int nt, const BatchInst<TS>* insts, const int2* items, int n_items, int mode,
+                            hipStream_t s);
+template <typename TS>
+hipError_t launch_decide_batch(const BatchInst<TS>* insts, int n_inst, int mode, hipStream_t s);
 
 int fx_num_waves(const ProbView& pv);
 int ftr_num_waves(const ProbView& pv);

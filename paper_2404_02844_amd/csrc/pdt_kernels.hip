@@ -184,7 +184,8 @@ __device__ __forceinline__ void reduce_tiles(const AccT (&acc)[NT], double* S, i
 // TS: storage type of X, O, R, P.  TC: MFMA operand type (TS, or float under TS = double
 // for the mixed path, whose forward product works on X_new - X_cur: FX_DELTA).
 template <typename TS, typename TC, int NT>
-__global__ __launch_bounds__(64 * KS) void fx_kernel(ProbView pv, Bufs<TS> b, SolverState* st, int mode) {
+__device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode, int tile,
+                                        int ntiles) {
   if ((mode == FX_ITER || mode == FX_DELTA) && st->done) return;
   typedef TS T;
   typedef typename Acc<TC>::type AccT;
@@ -197,7 +198,6 @@ __global__ __launch_bounds__(64 * KS) void fx_kernel(ProbView pv, Bufs<TS> b, So
   const int lane = tid & 63;
   const int i = lane & 15;
   const int kq = lane >> 4;
-  const int tile = blockIdx.x;
   const int M = pv.M, D = pv.D, N = pv.N, Npad = pv.Npad;
 
   const int ix_cur = st->ix_cur;
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(64 * KS) void fx_kernel(ProbView pv, Bufs<TS> b, So
   if (pv.gamma != 0.0 && M > 1) {
     double reg = 0.0;
     const long long pairs = (long long)(M - 1);
-    const long long W = gridDim.x;
+    const long long W = ntiles;
     const long long per = (pairs + W - 1) / W;
     const long long r0 = (long long)tile * per;
     const long long r1 = r0 + per < pairs ? r0 + per : pairs;
@@ -342,8 +342,8 @@ __global__ __launch_bounds__(64 * KS) void fx_kernel(ProbView pv, Bufs<TS> b, So
 // transposed as the MFMA A operand; the R rows of the next PF steps are prefetched.
 // ---------------------------------------------------------------------------------------
 template <typename TS, typename TC, int NT>
-__global__ __launch_bounds__(64 * KS) void ftr_kernel(ProbView pv, Bufs<TS> b, SolverState* st, int mode,
-                                                       double step) {
+__device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode,
+                                         double step, int mt) {
   if (mode == FTR_STEP && st->done) return;
   typedef TS T;
   typedef typename Acc<TC>::type AccT;
@@ -357,7 +357,6 @@ __global__ __launch_bounds__(64 * KS) void ftr_kernel(ProbView pv, Bufs<TS> b, S
   const int lane = tid & 63;
   const int i = lane & 15;
   const int kq = lane >> 4;
-  const int mt = blockIdx.x;
   const int m0 = mt << 4;
   const int M = pv.M, N = pv.N, Npad = pv.Npad;
   const int lumpm = pv.lump ? M - 1 : -1;
@@ -537,6 +536,35 @@ __global__ __launch_bounds__(64 * KS) void ftr_kernel(ProbView pv, Bufs<TS> b, S
   }
 }
 
+
+template <typename TS, typename TC, int NT>
+__global__ __launch_bounds__(64 * KS) void fx_kernel(ProbView pv, Bufs<TS> b, SolverState* st, int mode) {
+  fx_body<TS, TC, NT>(pv, b, st, mode, blockIdx.x, gridDim.x);
+}
+
+template <typename TS, typename TC, int NT>
+__global__ __launch_bounds__(64 * KS) void ftr_kernel(ProbView pv, Bufs<TS> b, SolverState* st, int mode,
+                                                       double step) {
+  ftr_body<TS, TC, NT>(pv, b, st, mode, step, blockIdx.x);
+}
+
+// Batched launches: one workgroup per (instance, tile) item of a work list; every
+// instance carries its own problem view, buffers, state and step.
+template <typename TS, typename TC, int NT>
+__global__ __launch_bounds__(64 * KS) void fx_batch_kernel(const BatchInst<TS>* insts, const int2* items, int mode) {
+  const int2 it = items[blockIdx.x];
+  const BatchInst<TS>& I = insts[it.x];
+  fx_body<TS, TC, NT>(I.pv, I.b, I.st, mode, it.y, I.n_dt);
+}
+
+template <typename TS, typename TC, int NT>
+__global__ __launch_bounds__(64 * KS) void ftr_batch_kernel(const BatchInst<TS>* insts, const int2* items,
+                                                             int mode) {
+  const int2 it = items[blockIdx.x];
+  const BatchInst<TS>& I = insts[it.x];
+  ftr_body<TS, TC, NT>(I.pv, I.b, I.st, mode, I.step, it.y);
+}
+
 // ---------------------------------------------------------------------------------------
 // Fixed-order reduction of the partials and the accept/reject decision.
 // ---------------------------------------------------------------------------------------
@@ -551,8 +579,8 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
   return sh[0];
 }
 
-__global__ __launch_bounds__(256) void decide_kernel(const double* partials, int n, SolverState* st,
-                                                     double* history, int mode) {
+__device__ __forceinline__ void decide_body(const double* partials, int n, SolverState* st, double* history,
+                                            int mode) {
   __shared__ double sh[256];
   if (mode == DEC_ITER && st->done) return;
   double s = 0.0;
@@ -603,6 +631,17 @@ __global__ __launch_bounds__(256) void decide_kernel(const double* partials, int
   st->iter = k + 1;
   if (k + 1 >= st->max_iters) st->done = 1;
   if (st->f_star > 0.0 && st->f_cur - st->f_star <= st->rel_tol * st->f_star) st->done = 1;
+}
+
+__global__ __launch_bounds__(256) void decide_kernel(const double* partials, int n, SolverState* st,
+                                                     double* history, int mode) {
+  decide_body(partials, n, st, history, mode);
+}
+
+template <typename TS>
+__global__ __launch_bounds__(256) void decide_batch_kernel(const BatchInst<TS>* insts, int mode) {
+  const BatchInst<TS>& I = insts[blockIdx.x];
+  decide_body(I.b.partials, I.n_dt, I.st, I.b.history, mode);
 }
 
 __global__ __launch_bounds__(256) void reduce_sum_kernel(const double* partials, int n, double* out) {
@@ -808,6 +847,51 @@ hipError_t launch_ftr(const ProbView& pv, const Bufs<TS>& b, SolverState* st, in
 #undef PDT_FTR
   return hipGetLastError();
 }
+
+template <typename TS, typename TC, int NT>
+static void fxb_go(const BatchInst<TS>* insts, const int2* items, int n_items, int mode, hipStream_t s) {
+  hipLaunchKernelGGL((fx_batch_kernel<TS, TC, NT>), dim3(n_items), dim3(64 * KS), 0, s, insts, items, mode);
+}
+template <typename TS, typename TC, int NT>
+static void ftrb_go(const BatchInst<TS>* insts, const int2* items, int n_items, int mode, hipStream_t s) {
+  hipLaunchKernelGGL((ftr_batch_kernel<TS, TC, NT>), dim3(n_items), dim3(64 * KS), 0, s, insts, items, mode);
+}
+
+template <typename TS, typename TC>
+hipError_t launch_fx_batch(int nt, const BatchInst<TS>* insts, const int2* items, int n_items, int mode,
+                           hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+#define PDT_FXB(K) fxb_go<TS, TC, K>(insts, items, n_items, mode, s)
+  PDT_NT_SWITCH(nt, PDT_FXB)
+#undef PDT_FXB
+  return hipGetLastError();
+}
+
+template <typename TS, typename TC>
+hipError_t launch_ftr_batch(int nt, const BatchInst<TS>* insts, const int2* items, int n_items, int mode,
+                            hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+#define PDT_FTRB(K) ftrb_go<TS, TC, K>(insts, items, n_items, mode, s)
+  PDT_NT_SWITCH(nt, PDT_FTRB)
+#undef PDT_FTRB
+  return hipGetLastError();
+}
+
+template <typename TS>
+hipError_t launch_decide_batch(const BatchInst<TS>* insts, int n_inst, int mode, hipStream_t s) {
+  if (n_inst <= 0) return hipSuccess;
+  hipLaunchKernelGGL((decide_batch_kernel<TS>), dim3(n_inst), dim3(256), 0, s, insts, mode);
+  return hipGetLastError();
+}
+
+template hipError_t launch_fx_batch<double, double>(int, const BatchInst<double>*, const int2*, int, int, hipStream_t);
+template hipError_t launch_fx_batch<float, float>(int, const BatchInst<float>*, const int2*, int, int, hipStream_t);
+template hipError_t launch_fx_batch<double, float>(int, const BatchInst<double>*, const int2*, int, int, hipStream_t);
+template hipError_t launch_ftr_batch<double, double>(int, const BatchInst<double>*, const int2*, int, int, hipStream_t);
+template hipError_t launch_ftr_batch<float, float>(int, const BatchInst<float>*, const int2*, int, int, hipStream_t);
+template hipError_t launch_ftr_batch<double, float>(int, const BatchInst<double>*, const int2*, int, int, hipStream_t);
+template hipError_t launch_decide_batch<double>(const BatchInst<double>*, int, int, hipStream_t);
+template hipError_t launch_decide_batch<float>(const BatchInst<float>*, int, int, hipStream_t);
 
 hipError_t launch_decide(const double* partials, int n, SolverState* st, double* history, int mode,
                          hipStream_t s) {

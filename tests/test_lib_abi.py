@@ -63,3 +63,12 @@ def test_null_handles_are_rejected():
     assert L.pdt_project_simplex(None, None, 3, 3, None) == _pdt.PDT_ERR_INVALID_ARG
     L.pdt_destroy_problem(None)  # no-op
     assert "NULL" in _pdt.pdt_last_error()
+
+
+def test_model_create_rejects_bad_sizes():
+    L = _pdt.lib()
+    out = ctypes.c_void_p()
+    for sizes in ((0, 8, 8), (258, 0, 16), (258, 8, -1)):
+        st = L.pdt_model_create(*sizes, None, None, ctypes.byref(out))
+        assert st == _pdt.PDT_ERR_INVALID_ARG and not out.value
+    assert "sizes" in _pdt.pdt_last_error()

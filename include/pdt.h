@@ -89,8 +89,8 @@ typedef struct {
  * the lumped tail mass) and the Lipschitz constant L = 1.05 * lambda_max(2 F^T F +
  * 2 gamma L_path) of the gradient by 100 FP64 power iterations.  stream: a hipStream_t
  * (NULL = the default stream); all later calls on the problem use it.  On error
- * nothing is allocated and *out is set to NULL.  n_instances must be 1 (reserved for
- * batches).
+ * nothing is allocated and *out is set to NULL.  n_instances >= 2 makes a batch
+ * (descs[k] per instance) for pdt_solve_batch.
  */
 pdt_status pdt_make_problem(const pdt_problem_desc* descs, int64_t n_instances, void* stream,
                             pdt_problem_t* out);
@@ -129,6 +129,19 @@ typedef struct {
  */
 pdt_status pdt_solve(pdt_problem_t problem, double* Pi, const pdt_solve_opts* opts,
                      pdt_solve_info* info);
+
+/*
+ * Solves every instance of a problem made with n_instances > 1 (uneven M and N allowed)
+ * together: each phase of an iteration is one launch per column-tile class (16 * nt
+ * outcome columns) over a work list of (instance, tile) items, ordered by decreasing
+ * band work; 64 iterations are captured in one graph and replayed until every instance
+ * reports done.  Pi: host array [n_instances] of device pointers, Pi[k] = [M_k * N_k].
+ * f_star: host [n_instances] (nullable) per-instance optimum for the tolerance test.
+ * info: host [n_instances] (nullable).  precision: PDT_FP64 or PDT_FP32; no history.
+ * pdt_solve, pdt_objective and pdt_kkt act on instance 0 of such a problem.
+ */
+pdt_status pdt_solve_batch(pdt_problem_t problem, double* const* Pi, const pdt_solve_opts* opts,
+                           const double* f_star, pdt_solve_info* info);
 
 /*
  * f(Pi) (FP64) and optionally its gradient 2 F^T (F Pi - P) + 2 gamma L_path Pi

@@ -97,6 +97,9 @@ def lib() -> ctypes.CDLL:
         for name in ("pdt_model_create", "pdt_model_get_params", "pdt_model_forward", "pdt_model_gradients",
                      "pdt_model_train_step", "pdt_warmstart_features"):
             getattr(L, name).restype = ctypes.c_int
+        L.pdt_solve_batch.argtypes = [vp, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(pdt_solve_opts), dp,
+                                      ctypes.POINTER(pdt_solve_info)]
+        L.pdt_solve_batch.restype = ctypes.c_int
         L.pdt_last_error.argtypes = []
         L.pdt_last_error.restype = ctypes.c_char_p
         for name in ("pdt_make_problem", "pdt_solve", "pdt_objective", "pdt_kkt", "pdt_project_simplex",
@@ -342,3 +345,61 @@ def pdt_warmstart_features(handle, X) -> int:
     bins = ctypes.c_int64()
     _check(lib().pdt_warmstart_features(handle, _dptr(X), ctypes.byref(bins)))
     return bins.value
+
+
+# ---- batches -------------------------------------------------------------------------------
+
+class BatchProblem:
+    """Several independent instances (uneven M, N, D) solved together by pdt_solve_batch."""
+
+    def __init__(self, instances, stream=None):
+        import numpy as np
+        self.instances = list(instances)
+        n = len(self.instances)
+        descs = (pdt_problem_desc * n)()
+        self._keep = []
+        for k, inst in enumerate(self.instances):
+            mu = np.ascontiguousarray(inst.mu, dtype=np.float64)
+            P = np.ascontiguousarray(inst.P, dtype=np.float64)
+            self._keep += [mu, P]
+            d = descs[k]
+            d.M, d.N, d.D = int(inst.M), int(P.shape[1]), int(mu.shape[0])
+            d.mu = mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            d.P = P.ctypes.data_as(ctypes.c_void_p)
+            d.P_on_device = 0
+            d.gamma = float(inst.gamma)
+            d.pmf_threshold = float(inst.threshold)
+            d.tail_mode = int(inst.tail_mode)
+        out = ctypes.c_void_p()
+        _check(lib().pdt_make_problem(descs, n, _stream_ptr(stream), ctypes.byref(out)))
+        self.handle = out
+
+    def solve(self, Pis, *, precision=PDT_FP64, init=PDT_INIT_UNIFORM, max_iters=1000, rel_obj_tol=0.0,
+              f_star=None, step_L=0.0):
+        import numpy as np
+        n = len(self.instances)
+        ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() for t in Pis])
+        o = pdt_solve_opts(precision=precision, init=init, max_iters=int(max_iters), rel_obj_tol=float(rel_obj_tol),
+                           f_star=0.0, step_L=float(step_L), history=None, model=None)
+        fs = None
+        if f_star is not None:
+            self._fs = np.ascontiguousarray(f_star, dtype=np.float64)
+            fs = self._fs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        infos = (pdt_solve_info * n)()
+        st = _check(lib().pdt_solve_batch(self.handle, ptrs, ctypes.byref(o), fs, infos),
+                    allow=(PDT_ERR_NOT_CONVERGED,))
+        out = [i.as_dict() for i in infos]
+        for d in out:
+            d["status"] = st
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pdt_destroy_problem(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

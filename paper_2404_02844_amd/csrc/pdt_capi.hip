@@ -113,9 +113,21 @@ struct Instance {
 
 struct pdt_model_s;
 
+struct BatchPlan {
+  int prec = -1;
+  std::vector<double> steps;
+  void* insts = nullptr;          // device BatchInst<T>[n]
+  std::vector<int> nt_class;      // column-tile class of each launch group
+  std::vector<int2*> fx_items, ftr_items;
+  std::vector<int> n_fx, n_ftr;
+  hipGraphExec_t graph = nullptr;
+};
+
 struct pdt_problem_s {
   hipStream_t stream = nullptr;
   hipStream_t capture = nullptr;  // library-owned stream used only to record graphs
+  BatchPlan plan;
+  Arena plan_arena;
   int device = 0;
   Arena arena;
   std::vector<Instance> inst;
@@ -569,7 +581,7 @@ pdt_status pdt_make_problem(const pdt_problem_desc* descs, int64_t n_instances, 
   if (!out) return set_err(PDT_ERR_INVALID_ARG, "out must not be NULL");
   *out = nullptr;
   if (!descs) return set_err(PDT_ERR_INVALID_ARG, "descs must not be NULL");
-  if (n_instances != 1) return set_err(PDT_ERR_INVALID_ARG, "n_instances must be 1");
+  if (n_instances < 1 || n_instances > 65536) return set_err(PDT_ERR_INVALID_ARG, "n_instances must be in [1, 65536]");
   pdt_problem_s* pb = nullptr;
   try {
     for (int64_t k = 0; k < n_instances; ++k) validate_desc(descs[k]);
@@ -595,6 +607,8 @@ void pdt_destroy_problem(pdt_problem_t problem) {
   if (!problem) return;
   (void)hipStreamSynchronize(problem->stream);
   for (Instance& I : problem->inst) drop_graphs(I);
+  if (problem->plan.graph) (void)hipGraphExecDestroy(problem->plan.graph);
+  problem->plan_arena.release();
   if (problem->capture) (void)hipStreamDestroy(problem->capture);
   problem->arena.release();
   delete problem;
@@ -1055,3 +1069,218 @@ int learned_start(pdt_problem_s* pb, Instance& I, pdt_model_s* md) {
 }
 
 }  // namespace
+
+// =======================================================================================
+// Batched solve: every instance of the problem, one launch per phase and column-tile
+// class over work lists of (instance, tile) items ordered by decreasing band work.
+// =======================================================================================
+namespace {
+
+template <typename T>
+void build_plan(pdt_problem_s* pb, int prec, const std::vector<double>& steps) {
+  BatchPlan& P = pb->plan;
+  if (P.prec == prec && P.steps == steps) return;
+  if (P.graph) (void)hipGraphExecDestroy(P.graph);
+  P = BatchPlan();
+  pb->plan_arena.release();
+  hipStream_t s = pb->stream;
+  const size_t n = pb->inst.size();
+  std::vector<BatchInst<T>> host(n);
+  // per column-tile class: items with their band work as the cost
+  std::vector<std::vector<std::pair<int64_t, int2>>> fx(kMaxNT + 1), ftr(kMaxNT + 1);
+  for (size_t k = 0; k < n; ++k) {
+    Instance& I = pb->inst[k];
+    BatchInst<T> bi;
+    bi.pv = view_of(I);
+    bi.b = bufs_of(I, work_of<T>(I), nullptr);
+    bi.st = I.st;
+    bi.step = steps[k];
+    bi.n_dt = fx_num_waves(bi.pv);
+    bi.n_mt = ftr_num_waves(bi.pv);
+    host[k] = bi;
+    const int nt = (int)(I.Npad / 16);
+    for (int t = 0; t < bi.n_dt; ++t) {
+      int64_t lo = INT64_MAX, hi = -1;
+      for (int d = 16 * t; d < std::min<int64_t>(16 * t + 16, I.D); ++d) {
+        if (I.lo_h[d] > I.hi_h[d]) continue;
+        lo = std::min<int64_t>(lo, I.lo_h[d]);
+        hi = std::max<int64_t>(hi, I.hi_h[d]);
+      }
+      fx[nt].push_back({(hi >= lo ? hi - lo + 1 : 0) * nt, int2{(int)k, t}});
+    }
+    for (int t = 0; t < bi.n_mt; ++t) ftr[nt].push_back({(int64_t)nt, int2{(int)k, t}});
+  }
+  P.insts = pb->plan_arena.alloc<BatchInst<T>>(n);
+  HIPCHK(hipMemcpyAsync(P.insts, host.data(), n * sizeof(BatchInst<T>), hipMemcpyHostToDevice, s));
+  for (int nt = 1; nt <= kMaxNT; ++nt) {
+    if (fx[nt].empty() && ftr[nt].empty()) continue;
+    auto by_cost = [](const std::pair<int64_t, int2>& a, const std::pair<int64_t, int2>& b) {
+      return a.first > b.first;
+    };
+    std::stable_sort(fx[nt].begin(), fx[nt].end(), by_cost);
+    std::vector<int2> a, c;
+    for (auto& e : fx[nt]) a.push_back(e.second);
+    for (auto& e : ftr[nt]) c.push_back(e.second);
+    int2* da = pb->plan_arena.alloc<int2>(a.size());
+    int2* dc = pb->plan_arena.alloc<int2>(c.size());
+    HIPCHK(hipMemcpyAsync(da, a.data(), a.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dc, c.data(), c.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    P.nt_class.push_back(nt);
+    P.fx_items.push_back(da);
+    P.ftr_items.push_back(dc);
+    P.n_fx.push_back((int)a.size());
+    P.n_ftr.push_back((int)c.size());
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  P.prec = prec;
+  P.steps = steps;
+}
+
+template <typename T>
+void enqueue_batch_iters(pdt_problem_s* pb, int64_t iters, hipStream_t s) {
+  BatchPlan& P = pb->plan;
+  const BatchInst<T>* insts = static_cast<const BatchInst<T>*>(P.insts);
+  const int n = (int)pb->inst.size();
+  for (int64_t k = 0; k < iters; ++k) {
+    for (size_t c = 0; c < P.nt_class.size(); ++c)
+      HIPCHK((launch_ftr_batch<T, T>(P.nt_class[c], insts, P.ftr_items[c], P.n_ftr[c], FTR_STEP, s)));
+    for (size_t c = 0; c < P.nt_class.size(); ++c)
+      HIPCHK((launch_fx_batch<T, T>(P.nt_class[c], insts, P.fx_items[c], P.n_fx[c], FX_ITER, s)));
+    HIPCHK(launch_decide_batch<T>(insts, n, DEC_ITER, s));
+  }
+}
+
+template <typename T>
+void run_batch(pdt_problem_s* pb, const pdt_solve_opts& o, int prec, std::vector<SolverState>& out) {
+  hipStream_t s = pb->stream;
+  BatchPlan& P = pb->plan;
+  const BatchInst<T>* insts = static_cast<const BatchInst<T>*>(P.insts);
+  const int n = (int)pb->inst.size();
+  for (size_t c = 0; c < P.nt_class.size(); ++c)
+    HIPCHK((launch_fx_batch<T, T>(P.nt_class[c], insts, P.fx_items[c], P.n_fx[c], FX_INIT, s)));
+  HIPCHK(launch_decide_batch<T>(insts, n, DEC_INIT, s));
+  if (o.max_iters >= kGraphIters && !P.graph) {
+    if (!pb->capture) HIPCHK(hipStreamCreateWithFlags(&pb->capture, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(pb->capture, hipStreamCaptureModeThreadLocal));
+    try {
+      enqueue_batch_iters<T>(pb, kGraphIters, pb->capture);
+    } catch (...) {
+      (void)hipStreamEndCapture(pb->capture, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIPCHK(hipStreamEndCapture(pb->capture, &g));
+    hipError_t e = hipGraphInstantiate(&P.graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(e);
+  }
+  std::vector<SolverState> st(n);
+  int64_t launched = 0;
+  while (launched < o.max_iters) {
+    if (o.max_iters - launched >= kGraphIters) {
+      HIPCHK(hipGraphLaunch(P.graph, s));
+      launched += kGraphIters;
+    } else {
+      enqueue_batch_iters<T>(pb, o.max_iters - launched, s);
+      launched = o.max_iters;
+    }
+    bool all = true;
+    for (int k = 0; k < n; ++k) {
+      st[k] = read_state(s, pb->inst[k].st);
+      all = all && st[k].done;
+    }
+    if (all) break;
+  }
+  for (int k = 0; k < n; ++k) st[k] = read_state(s, pb->inst[k].st);
+  out = st;
+}
+
+}  // namespace
+
+extern "C" {
+
+pdt_status pdt_solve_batch(pdt_problem_t pb, double* const* Pi, const pdt_solve_opts* opts, const double* f_star,
+                           pdt_solve_info* info) {
+  if (!pb || !Pi || !opts) return set_err(PDT_ERR_INVALID_ARG, "problem, Pi and opts must not be NULL");
+  const pdt_solve_opts o = *opts;
+  const size_t n = pb->inst.size();
+  if (o.max_iters < 0 || !std::isfinite(o.rel_obj_tol) || o.rel_obj_tol < 0)
+    return set_err(PDT_ERR_INVALID_ARG, "bad max_iters or tolerance");
+  if (o.precision != PDT_FP64 && o.precision != PDT_FP32) return set_err(PDT_ERR_INVALID_ARG, "batch precision must be FP64 or FP32");
+  if (o.init != PDT_INIT_UNIFORM && o.init != PDT_INIT_USER) return set_err(PDT_ERR_INVALID_ARG, "bad init");
+  if (o.history) return set_err(PDT_ERR_INVALID_ARG, "history is not supported for batches");
+  for (size_t k = 0; k < n; ++k)
+    if (!Pi[k]) return set_err(PDT_ERR_INVALID_ARG, "Pi[k] must not be NULL");
+  const auto t0 = std::chrono::steady_clock::now();
+  try {
+    hipStream_t s = pb->stream;
+    Arena& A = pb->arena;
+    std::vector<double> steps(n);
+    for (size_t k = 0; k < n; ++k) {
+      Instance& I = pb->inst[k];
+      ensure_work<double>(A, I, I.w64, I.P64);
+      const size_t Np = (size_t)I.Npad, N = (size_t)I.N, M = (size_t)I.M;
+      steps[k] = 1.0 / (o.step_L > 0 ? o.step_L : I.L_hat);
+      if (o.init == PDT_INIT_USER) HIPCHK(launch_project_rows<double>(Pi[k], I.w64.X[0], (long long)M, (int)N, (int)N, (int)Np, s));
+      else HIPCHK(launch_fill_rows<double>(I.w64.X[0], (long long)M, (int)N, (int)Np, 1.0 / (double)N, s));
+      const double fs = (f_star && f_star[k] > 0) ? f_star[k] : 0.0;
+      init_state(s, I.st, o.max_iters, fs, o.rel_obj_tol);
+      if (o.precision == PDT_FP32) {
+        if (!I.P32) {
+          I.P32 = A.alloc<float>((size_t)I.D * Np);
+          HIPCHK(launch_convert_pad<double, float>(I.P64, I.P32, (long long)I.D, (int)Np, (int)Np, (int)Np, s));
+        }
+        ensure_work<float>(A, I, I.w32, I.P32);
+        HIPCHK(launch_convert_pad<double, float>(I.w64.X[0], I.w32.X[0], (long long)M, (int)Np, (int)Np, (int)Np, s));
+      }
+    }
+    std::vector<SolverState> fin;
+    if (o.precision == PDT_FP64) {
+      build_plan<double>(pb, PDT_FP64, steps);
+      run_batch<double>(pb, o, PDT_FP64, fin);
+    } else {
+      build_plan<float>(pb, PDT_FP32, steps);
+      run_batch<float>(pb, o, PDT_FP32, fin);
+    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    bool all_conv = true;
+    for (size_t k = 0; k < n; ++k) {
+      Instance& I = pb->inst[k];
+      const size_t Np = (size_t)I.Npad, N = (size_t)I.N, M = (size_t)I.M;
+      if (o.precision == PDT_FP64) {
+        if (fin[k].ix_cur != 0)
+          HIPCHK(hipMemcpyAsync(I.w64.X[0], I.w64.X[fin[k].ix_cur], M * Np * sizeof(double), hipMemcpyDeviceToDevice, s));
+      } else {
+        HIPCHK(launch_convert_pad<float, double>(I.w32.X[fin[k].ix_cur], I.w64.X[0], (long long)M, (int)Np, (int)Np,
+                                                 (int)Np, s));
+      }
+      double kkt = 0;
+      const double f = eval_fp64(pb, I, true, &kkt);
+      HIPCHK(hipMemcpy2DAsync(Pi[k], N * sizeof(double), I.w64.X[0], Np * sizeof(double), N * sizeof(double), M,
+                              hipMemcpyDeviceToDevice, s));
+      const double fs = (f_star && f_star[k] > 0) ? f_star[k] : 0.0;
+      const bool conv = fs > 0 && fin[k].f_cur - fs <= o.rel_obj_tol * fs;
+      all_conv = all_conv && (conv || fs <= 0 || o.rel_obj_tol <= 0);
+      if (info) {
+        info[k].iters = fin[k].iter;
+        info[k].rejects = fin[k].rejects;
+        info[k].objective = f;
+        info[k].kkt = kkt;
+        info[k].L_used = 1.0 / steps[k];
+        info[k].seconds = secs;
+        info[k].converged = conv ? 1 : 0;
+        info[k].refine_iters = 0;
+        info[k].fell_back_to_cold = 0;
+      }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (!all_conv) return set_err(PDT_ERR_NOT_CONVERGED, "max_iters reached before the tolerance for some instance");
+    g_last_error.clear();
+    return PDT_OK;
+  } catch (...) {
+    return status_of_current_exception();
+  }
+}
+
+}  // extern "C"

@@ -33,6 +33,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+PROFILE = os.path.join(ROOT, "profiles", "ftr_kernel_c2_m4096_n65_d5000.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the transposed product from the committed FETCH_SIZE /
+    WRITE_SIZE summary, or None once the kernel source differs from the profiled one."""
+    import hashlib
+    try:
+        text = open(PROFILE).read()
+        src = open(os.path.join(ROOT, "paper_2404_02844_amd", "csrc", "pdt_kernels.hip"), "rb").read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and line[:1].isalpha()
+                  and line.split(": ", 1)[0] in ("kernel_source_sha256", "ftr_bytes_per_launch"))
+    if fields.get("kernel_source_sha256", "").strip() != hashlib.sha256(src).hexdigest():
+        return None
+    return float(fields["ftr_bytes_per_launch"])
+
+
 def cpu_baseline(inst, seconds=12.0):
     """The oracle's iteration on a bounded number of iterations of the same workload."""
     from oracle import fista, poisson
@@ -160,7 +179,7 @@ def main():
     flops = 2.0 * nnz * N
     achieved = flops / times["ftr"] / 1e12
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(),
                 "kernel": "ftr_kernel<double> (F^T R band product + projected step)",
                 "per_launch_flops": flops, "avg_launch_s": times["ftr"],
                 "fx_avg_launch_s": times["fx"], "iteration_s": times["iteration"]}

@@ -46,6 +46,12 @@ def solve_pair(inst, *, max_iters: int, precision=_pdt.PDT_MIXED, start_from_tru
     return Pair(X=X, T=T, iters=int(info["iters"]), f=float(info["objective"]))
 
 
+def init_layers(rng: np.random.Generator, sizes) -> list:
+    """Initial weights W ~ N(0, 1/fan_in) ([out, in]) and zero biases."""
+    return [(rng.normal(0.0, 1.0 / np.sqrt(fin), size=(fout, fin)), np.zeros(fout))
+            for fin, fout in zip(sizes[:-1], sizes[1:])]
+
+
 def train(model: "_pdt.Model", pairs, *, epochs: int, batch: int = 256, lr: float = 1e-3, seed: int = 0,
           lr_decay: float = 1.0, log_every: int = 0):
     """Adam over the rows of all pairs, shuffled every epoch; returns the loss history."""

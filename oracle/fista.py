@@ -19,6 +19,19 @@ gradient step of length 1/L_hat, which decreases f when L_hat >= lambda_max.
 
 L_hat = 1.05 * lambda_max(2 F^T F + 2 gamma L), lambda_max from 100 power iterations
 started at the unit vector 1/sqrt(M): lambda_k = ||H v_{k-1}||, v_k = H v_{k-1} / lambda_k.
+
+Row-scaled step (optional).  The paper preconditions its CG solves with the diagonal
+of the Hessian (Table "ops": diagonal of the Hessian; App. B).  For this objective
+that diagonal does not depend on the outcome column:
+
+    h_m = 2 sum_d F[d][m]^2 + 2 gamma L[m][m]        (L[m][m] = 1 at the ends, 2 inside)
+
+so a step scaled by 1/h_m per row of Pi keeps the constraint structure: each row is
+scaled uniformly, and the projection in the metric diag(h) onto the product of row
+simplices is still the row-wise Euclidean projection.  The step becomes
+X' = P_{S^M}(Y - diag(w) G / L_w) with w_m = 1/max(h_m, 1e-12 max h) and
+L_w = 1.05 * lambda_max(W^{1/2} H W^{1/2}) from the same 100-step power iteration
+(the momentum method run in the variables W^{-1/2} Pi).
 """
 from __future__ import annotations
 
@@ -47,6 +60,40 @@ def lipschitz(F, gamma: float, M: int, iters: int = 100, safety: float = 1.05) -
     return safety * lam
 
 
+def hessian_diag(F, gamma: float, M: int) -> np.ndarray:
+    """h_m = 2 sum_d F[d][m]^2 + 2 gamma L[m][m] (the Hessian diagonal, per row)."""
+    Fd = F.toarray() if hasattr(F, "toarray") else np.asarray(F)
+    ldiag = np.zeros(M)
+    if M >= 2:
+        ldiag[:] = 2.0
+        ldiag[0] = ldiag[-1] = 1.0
+    return np.array([2.0 * math.fsum(Fd[:, m] ** 2) for m in range(M)]) + 2.0 * gamma * ldiag
+
+
+def row_weights(F, gamma: float, M: int) -> np.ndarray:
+    """w_m = 1 / max(h_m, 1e-12 max_m h_m); all ones when h vanishes."""
+    h = hessian_diag(F, gamma, M)
+    hmax = float(np.max(h)) if M else 0.0
+    if hmax <= 0.0:
+        return np.ones(M)
+    return 1.0 / np.maximum(h, 1e-12 * hmax)
+
+
+def lipschitz_scaled(F, gamma: float, M: int, w: np.ndarray, iters: int = 100,
+                     safety: float = 1.05) -> float:
+    """1.05 * lambda_max(W^{1/2} H W^{1/2}) by power iteration from 1/sqrt(M)."""
+    sw = np.sqrt(w)
+    v = np.full(M, 1.0 / math.sqrt(M))
+    lam = 0.0
+    for _ in range(iters):
+        z = sw * hessian_apply(F, gamma, sw * v)
+        lam = math.sqrt(math.fsum(z * z))
+        if lam == 0.0:
+            break
+        v = z / lam
+    return safety * lam
+
+
 @dataclasses.dataclass
 class FistaResult:
     X: np.ndarray
@@ -59,11 +106,13 @@ class FistaResult:
 
 def fista_r(F, P: np.ndarray, gamma: float, L_hat: float, iters: int,
             X0: np.ndarray | None = None, exact_sums: bool = True,
-            f_star: float | None = None, rel_tol: float | None = None) -> FistaResult:
+            f_star: float | None = None, rel_tol: float | None = None,
+            row_w: np.ndarray | None = None) -> FistaResult:
+    """row_w: per-row step weights w (the step of row m is w_m / L_hat); None: w = 1."""
     M = F.shape[1]
     N = P.shape[1]
     X = project_rows(np.full((M, N), 1.0 / N) if X0 is None else X0)
-    s = 1.0 / L_hat
+    s = 1.0 / L_hat if row_w is None else (np.asarray(row_w, dtype=np.float64) / L_hat)[:, None]
 
     def fval(O, Xc):
         return sum_squares(O - P, exact_sums) + regulariser(Xc, gamma, exact_sums)

@@ -4,13 +4,16 @@ Workload (one "step"): solve the M=4096, N=65, D=5000 problem (64-bin click dete
 efficiency 0.85, dark counts 1e-4 per bin, probes with mu linearly spaced on [0, 4500],
 F band above 1e-16 with the tail lumped into the last column, 1e7 shots per probe,
 gamma = 1e-4) from the uniform start Pi = 1/N to a relative objective error of 1e-9
-against a reference optimum, in FP64, with inputs already resident in HBM.
+against a reference optimum, in FP64 with the row-scaled step (per-row step from the
+Hessian diagonal), with inputs already resident in HBM.
 
-Reported value: POVM elements x iterations per second (M * N * iterations / time) of
-the timed FP64 solves.  Beside it: the time to tolerance, the FP32 solve (relative
-objective 1e-4), the roofline of the dominant kernel (average launch duration from
-HIP events on the stream the kernel runs on), and the CPU oracle timed on a bounded
-sample of the same iteration.
+The reference optimum is a 30000-iteration FP64 solve with the scaled step, reported
+with its KKT residual.  Reported value: POVM elements x iterations per second
+(M * N * iterations / time) of the timed FP64 solves.  Beside it: the time to
+tolerance; the same solve with the uniform step 1/L (capped at 60000 iterations, with
+the relative objective it reached); the mixed-precision and FP32 solves; the roofline
+of the dominant kernel (average launch duration from HIP events on the stream the
+kernel runs on); and the CPU oracle timed on a bounded sample of the same iteration.
 """
 import argparse
 import json
@@ -119,18 +122,20 @@ def main():
         log("[bench] kernels-only pass done")
         return
 
-    # reference optimum: a long FP64 solve, certified by its KKT residual
+    # reference optimum: a long FP64 solve with the scaled step, certified by its KKT residual
+    DIAG, UNIFORM = _pdt.PDT_STEP_DIAG, _pdt.PDT_STEP_UNIFORM
     t0 = time.perf_counter()
-    ref_iters = 60000
-    info_ref = pb.solve(Pi, max_iters=ref_iters)
+    ref_iters = 30000
+    info_ref = pb.solve(Pi, max_iters=ref_iters, scaling=DIAG)
     f_ref = info_ref["objective"]
     log(f"[bench] reference: f={f_ref:.16e} kkt={info_ref['kkt']:.3e} iters={info_ref['iters']} "
         f"({time.perf_counter() - t0:.1f} s)")
 
-    def solve(precision, tol):
+    def solve(precision, tol, scaling=DIAG, max_iters=200000):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        info = pb.solve(Pi, precision=precision, max_iters=200000, rel_obj_tol=tol, f_star=f_ref)
+        info = pb.solve(Pi, precision=precision, max_iters=max_iters, rel_obj_tol=tol, f_star=f_ref,
+                        scaling=scaling)
         torch.cuda.synchronize()
         info["wall"] = time.perf_counter() - t
         return info
@@ -147,8 +152,12 @@ def main():
     for r in runs:
         log(f"[bench] fp64 solve: iters={r['iters']} wall={r['wall']:.3f}s converged={r['converged']} "
             f"relobj={(r['objective'] - f_ref) / f_ref:.2e}")
-    fp32 = solve(_pdt.PDT_FP32, 1e-4)
-    log(f"[bench] fp32 solve: iters={fp32['iters']} wall={fp32['wall']:.3f}s converged={fp32['converged']}")
+    uni = solve(_pdt.PDT_FP64, args.tol, scaling=UNIFORM, max_iters=60000)
+    log(f"[bench] fp64 uniform-step solve: iters={uni['iters']} wall={uni['wall']:.3f}s converged={uni['converged']} "
+        f"relobj={(uni['objective'] - f_ref) / f_ref:.2e}")
+    fp32 = solve(_pdt.PDT_FP32, 1e-4, max_iters=20000)
+    log(f"[bench] fp32 solve: iters={fp32['iters']} wall={fp32['wall']:.3f}s converged={fp32['converged']} "
+        f"relobj={(fp32['objective'] - f_ref) / f_ref:.2e}")
     mixed = [solve(_pdt.PDT_MIXED, args.tol) for _ in range(max(1, args.steps))]
     for r in mixed:
         log(f"[bench] mixed solve: iters={r['iters']} (fp64 refinement {r['refine_iters']}) wall={r['wall']:.3f}s "
@@ -202,10 +211,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": inst.name, "M": M, "N": N, "D": D, "gamma": inst.gamma,
                    "pmf_threshold": inst.threshold, "tail": "lump", "tolerance": args.tol,
-                   "band_entries": nnz},
+                   "band_entries": nnz, "step": "row-scaled (Hessian diagonal)"},
         "time_to_tol_s": float(np.median([r["wall"] for r in runs])),
         "iters_to_tol": int(np.median([r["iters"] for r in runs])),
         "f_ref": f_ref,
+        "f_ref_kkt": info_ref["kkt"],
+        "uniform_step_fp64": {"time_s": uni["wall"], "iters": uni["iters"], "converged": uni["converged"],
+                              "relobj": (uni["objective"] - f_ref) / f_ref, "max_iters": 60000},
         "mixed": {"time_to_tol_s": float(np.median([r["wall"] for r in mixed])),
                   "iters": int(np.median([r["iters"] for r in mixed])),
                   "refine_iters": int(np.median([r["refine_iters"] for r in mixed])),
@@ -213,7 +225,7 @@ def main():
                   "relobj": float(max((r["objective"] - f_ref) / f_ref for r in mixed)),
                   "speedup_vs_fp64": float(np.median([r["wall"] for r in runs]) /
                                            np.median([r["wall"] for r in mixed]))},
-        "fp32": {"time_to_tol_s": fp32["wall"], "iters": fp32["iters"], "tol": 1e-4,
+        "fp32": {"time_s": fp32["wall"], "iters": fp32["iters"], "tol": 1e-4, "max_iters": 20000,
                  "converged": fp32["converged"], "relobj": (fp32["objective"] - f_ref) / f_ref},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -230,7 +242,8 @@ def _gen_c4(i):
 
 def bench_batch(args, count=256, iters=2000):
     """256 detectors (M ~ U{256..8192}, N = bins + 1 with bins ~ U{8..128}, D = 1.2 M) solved
-    together by one batched FP32 solve of a fixed number of iterations."""
+    together by one batched FP32 solve of a fixed number of iterations with the row-scaled
+    step (its Lipschitz constants are computed in the untimed warmup)."""
     import concurrent.futures as cf
     import torch
     from paper_2404_02844_amd import _pdt
@@ -244,11 +257,11 @@ def bench_batch(args, count=256, iters=2000):
     log(f"[bench] batch setup {time.perf_counter() - t0:.1f} s")
     Pis = [torch.zeros((i.M, i.N), dtype=torch.float64, device="cuda") for i in insts]
     for _ in range(args.warmup):
-        bp.solve(Pis, precision=_pdt.PDT_FP32, max_iters=128)
+        bp.solve(Pis, precision=_pdt.PDT_FP32, max_iters=128, scaling=_pdt.PDT_STEP_DIAG)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        infos = bp.solve(Pis, precision=_pdt.PDT_FP32, max_iters=iters)
+        infos = bp.solve(Pis, precision=_pdt.PDT_FP32, max_iters=iters, scaling=_pdt.PDT_STEP_DIAG)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / args.steps
     elems = sum(i.M * i.N for i in insts)
@@ -258,7 +271,8 @@ def bench_batch(args, count=256, iters=2000):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "c4_batch256", "instances": count, "iters": iters, "sum_MN": elems,
                    "M_range": [min(i.M for i in insts), max(i.M for i in insts)],
-                   "N_range": [min(i.N for i in insts), max(i.N for i in insts)]},
+                   "N_range": [min(i.N for i in insts), max(i.N for i in insts)],
+                   "step": "row-scaled (Hessian diagonal)"},
         "instances_per_s": count / el,
         "objective_range": [min(i["objective"] for i in infos), max(i["objective"] for i in infos)],
     }

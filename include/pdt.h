@@ -66,6 +66,19 @@ typedef enum {
                            falls back to 1/N when that start is not better */
 } pdt_init_mode;
 
+/*
+ * Step of row m of Pi.  UNIFORM: 1/L with L = 1.05 lambda_max(H), H = 2 F^T F + 2 gamma
+ * L_path.  DIAG: w_m / L_w with w_m = 1 / max(h_m, 1e-12 max h), h_m = 2 sum_d F[d][m]^2 +
+ * 2 gamma L_path[m][m] the Hessian diagonal (the diagonal the paper uses to precondition
+ * its CG solves, Table "ops" and App. B), and L_w = 1.05 lambda_max(W^(1/2) H W^(1/2)).
+ * The diagonal is the same for every outcome column, so each row is scaled uniformly and
+ * the projection stays the row-wise Euclidean one; the minimiser is unchanged.
+ */
+typedef enum {
+  PDT_STEP_UNIFORM = 0,
+  PDT_STEP_DIAG = 1
+} pdt_step_scaling;
+
 typedef struct pdt_model_s* pdt_model_t;
 
 /* One tomography instance (arguments follow Eq. min and Eq. Fmatrix). */
@@ -104,9 +117,11 @@ typedef struct {
   int64_t max_iters;      /* iterations of the momentum method, >= 0 */
   double rel_obj_tol;     /* stop once f - f_star <= rel_obj_tol * f_star (needs f_star > 0) */
   double f_star;          /* known optimum value; <= 0 disables the tolerance test */
-  double step_L;          /* step = 1 / step_L; 0 uses the problem's own Lipschitz estimate */
+  double step_L;          /* overrides the Lipschitz constant of the step (L, or L_w with
+                             scaling = DIAG); 0 uses the problem's own estimate */
   double* history;        /* optional device [max_iters]: f after each iteration (FP64) */
   pdt_model_t model;      /* warm-start network for init == PDT_INIT_LEARNED (n_in 258, n_out M) */
+  int scaling;            /* pdt_step_scaling */
 } pdt_solve_opts;
 
 typedef struct {
@@ -114,7 +129,7 @@ typedef struct {
   int64_t rejects;        /* candidate steps rejected (momentum restarts) */
   double objective;       /* f at the returned Pi, FP64 */
   double kkt;             /* KKT residual of App. B with lambda_i = -min_n df/dPi[i][n] */
-  double L_used;          /* Lipschitz constant used for the step */
+  double L_used;          /* Lipschitz constant used for the step (L_w with scaling = DIAG) */
   double seconds;         /* wall time of the call */
   int converged;          /* 1 if the tolerance test was met */
   int64_t refine_iters;   /* PDT_MIXED: iterations of the FP64 refinement (included in iters) */
@@ -171,6 +186,10 @@ pdt_status pdt_project_simplex_f32(const float* X, float* Y, int64_t rows, int64
  * number of band entries sum_d (hi_d - lo_d + 1) (host, nullable). */
 pdt_status pdt_problem_bands(pdt_problem_t problem, int32_t* lo, int32_t* hi, double* tail,
                              double* lipschitz, int64_t* nnz);
+
+/* Row scaling of instance 0 (see pdt_step_scaling): Hessian diagonal h (host [M],
+ * nullable) and L_w (host, nullable; 100 FP64 power iterations on first request). */
+pdt_status pdt_problem_scaling(pdt_problem_t problem, double* hdiag, double* lipschitz_scaled);
 
 /*
  * Warm-start network (learned initial Pi; not in the paper, whose runs start from

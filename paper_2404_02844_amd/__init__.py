@@ -6,4 +6,5 @@ The solver lives in the HIP library ``libpdt.so`` (C ABI in ``include/pdt.h``);
 from . import _pdt  # noqa: F401
 from ._pdt import (BatchProblem, PDT_FP32, PDT_FP64, PDT_INIT_LEARNED, PDT_MIXED, Model, pdt_warmstart_features, PDT_INIT_UNIFORM, PDT_INIT_USER, PDT_TAIL_LUMP,  # noqa: F401
                    PDT_TAIL_TRUNCATE, PdtError, Problem, pdt_destroy_problem, pdt_kkt, pdt_last_error,
-                   pdt_make_problem, pdt_objective, pdt_problem_bands, pdt_project_simplex, pdt_solve)
+                   pdt_make_problem, pdt_objective, pdt_problem_bands, pdt_problem_scaling, pdt_project_simplex, pdt_solve,
+                   PDT_STEP_UNIFORM, PDT_STEP_DIAG)

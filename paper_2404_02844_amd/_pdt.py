@@ -30,6 +30,9 @@ PDT_INIT_UNIFORM = 0
 PDT_INIT_USER = 1
 PDT_INIT_LEARNED = 2
 
+PDT_STEP_UNIFORM = 0
+PDT_STEP_DIAG = 1
+
 STATUS_NAMES = {0: "PDT_OK", 1: "PDT_ERR_INVALID_ARG", 2: "PDT_ERR_OUT_OF_MEMORY", 3: "PDT_ERR_DEVICE",
                 4: "PDT_ERR_NOT_CONVERGED", 5: "PDT_ERR_NUMERIC"}
 
@@ -50,7 +53,7 @@ class pdt_problem_desc(ctypes.Structure):
 class pdt_solve_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("init", ctypes.c_int), ("max_iters", ctypes.c_int64),
                 ("rel_obj_tol", ctypes.c_double), ("f_star", ctypes.c_double), ("step_L", ctypes.c_double),
-                ("history", ctypes.c_void_p), ("model", ctypes.c_void_p)]
+                ("history", ctypes.c_void_p), ("model", ctypes.c_void_p), ("scaling", ctypes.c_int)]
 
 
 class pdt_solve_info(ctypes.Structure):
@@ -82,6 +85,7 @@ def lib() -> ctypes.CDLL:
         L.pdt_project_simplex_f32.argtypes = [vp, vp, i64, i64, vp]
         L.pdt_problem_bands.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), dp, dp,
                                         ctypes.POINTER(ctypes.c_int64)]
+        L.pdt_problem_scaling.argtypes = [vp, dp, dp]
         L.pdt_replay_kernel.argtypes = [vp, ctypes.c_int, ctypes.c_int, i64]
         L.pdt_replay_kernel.restype = ctypes.c_int
         L.pdt_model_create.argtypes = [i64, i64, i64, vp, vp, ctypes.POINTER(vp)]
@@ -103,7 +107,7 @@ def lib() -> ctypes.CDLL:
         L.pdt_last_error.argtypes = []
         L.pdt_last_error.restype = ctypes.c_char_p
         for name in ("pdt_make_problem", "pdt_solve", "pdt_objective", "pdt_kkt", "pdt_project_simplex",
-                     "pdt_project_simplex_f32", "pdt_problem_bands"):
+                     "pdt_project_simplex_f32", "pdt_problem_bands", "pdt_problem_scaling"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -167,14 +171,15 @@ def pdt_destroy_problem(handle) -> None:
 
 
 def pdt_solve(handle, Pi, *, precision=PDT_FP64, init=PDT_INIT_UNIFORM, max_iters=1000, rel_obj_tol=0.0,
-              f_star=0.0, step_L=0.0, history=None, model=None, allow_not_converged=True) -> dict:
+              f_star=0.0, step_L=0.0, history=None, model=None, scaling=PDT_STEP_UNIFORM,
+              allow_not_converged=True) -> dict:
     """Solve in place: ``Pi`` is a contiguous float64 [M, N] GPU tensor."""
     if model is not None and init == PDT_INIT_UNIFORM:
         init = PDT_INIT_LEARNED
     o = pdt_solve_opts(precision=precision, init=init, max_iters=int(max_iters), rel_obj_tol=float(rel_obj_tol),
                        f_star=float(f_star), step_L=float(step_L),
                        history=ctypes.c_void_p(history.data_ptr()) if history is not None else None,
-                       model=(model.handle if isinstance(model, Model) else model))
+                       model=(model.handle if isinstance(model, Model) else model), scaling=int(scaling))
     info = pdt_solve_info()
     st = _check(lib().pdt_solve(handle, ctypes.c_void_p(Pi.data_ptr()), ctypes.byref(o), ctypes.byref(info)),
                 allow=(PDT_ERR_NOT_CONVERGED,) if allow_not_converged else ())
@@ -224,6 +229,14 @@ def pdt_problem_bands(handle, D: int) -> dict:
     return {"lo": lo, "hi": hi, "tail": tail, "lipschitz": L.value, "nnz": nnz.value}
 
 
+def pdt_problem_scaling(handle, M: int) -> dict:
+    import numpy as np
+    h = np.zeros(M, dtype=np.float64)
+    Lw = ctypes.c_double()
+    _check(lib().pdt_problem_scaling(handle, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(Lw)))
+    return {"hdiag": h, "lipschitz_scaled": Lw.value}
+
+
 class Problem:
     """Owns a problem handle; thin convenience over the pdt_* calls."""
 
@@ -248,6 +261,9 @@ class Problem:
 
     def bands(self):
         return pdt_problem_bands(self.handle, self.D)
+
+    def scaling(self):
+        return pdt_problem_scaling(self.handle, self.M)
 
     def close(self):
         if self.handle:
@@ -375,12 +391,12 @@ class BatchProblem:
         self.handle = out
 
     def solve(self, Pis, *, precision=PDT_FP64, init=PDT_INIT_UNIFORM, max_iters=1000, rel_obj_tol=0.0,
-              f_star=None, step_L=0.0):
+              f_star=None, step_L=0.0, scaling=PDT_STEP_UNIFORM):
         import numpy as np
         n = len(self.instances)
         ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() for t in Pis])
         o = pdt_solve_opts(precision=precision, init=init, max_iters=int(max_iters), rel_obj_tol=float(rel_obj_tol),
-                           f_star=0.0, step_L=float(step_L), history=None, model=None)
+                           f_star=0.0, step_L=float(step_L), history=None, model=None, scaling=int(scaling))
         fs = None
         if f_star is not None:
             self._fs = np.ascontiguousarray(f_star, dtype=np.float64)

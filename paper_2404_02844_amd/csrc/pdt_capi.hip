@@ -77,6 +77,7 @@ struct Instance {
   double gamma = 0, tau = 0;
   int lump = 0;
   double L_hat = 0;
+  double L_w = 0;  // 1.05 lambda_max(W^(1/2) H W^(1/2)) for the row-scaled step (0: not yet computed)
   int64_t nnz = 0;
   int bins = 0;  // last outcome column with any probability mass (outcomes 0..bins are real)
   std::vector<int> lo_h, hi_h;
@@ -95,6 +96,9 @@ struct Instance {
   int* mt_dhi = nullptr;
   double* P64 = nullptr;
   float* P32 = nullptr;
+  double* hdiag = nullptr;  // [M] Hessian diagonal per row
+  double* wrow = nullptr;   // [M] w_m = 1 / max(h_m, 1e-12 max h)
+  std::vector<double> hdiag_h, wrow_h;
   Work<double> w64;
   Work<float> w32;
   double* partials = nullptr;
@@ -107,6 +111,7 @@ struct Instance {
   hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
   double graph_step[3] = {0.0, 0.0, 0.0};
   double* graph_hist[3] = {nullptr, nullptr, nullptr};
+  const double* graph_w[3] = {nullptr, nullptr, nullptr};
 };
 
 }  // namespace
@@ -115,6 +120,7 @@ struct pdt_model_s;
 
 struct BatchPlan {
   int prec = -1;
+  int scaling = -1;
   std::vector<double> steps;
   void* insts = nullptr;          // device BatchInst<T>[n]
   std::vector<int> nt_class;      // column-tile class of each launch group
@@ -181,7 +187,7 @@ ProbView view_of(const Instance& I) {
 }
 
 template <typename T>
-Bufs<T> bufs_of(const Instance& I, const Work<T>& w, double* history) {
+Bufs<T> bufs_of(const Instance& I, const Work<T>& w, double* history, const double* wrow = nullptr) {
   Bufs<T> b;
   for (int k = 0; k < 3; ++k) {
     b.X[k] = w.X[k];
@@ -194,6 +200,7 @@ Bufs<T> bufs_of(const Instance& I, const Work<T>& w, double* history) {
   b.partials = I.partials;
   b.n_partials = I.n_partials;
   b.history = history;
+  b.wrow = wrow;
   return b;
 }
 
@@ -236,8 +243,9 @@ void validate_desc(const pdt_problem_desc& d) {
   }
 }
 
-// Power iteration for lambda_max(2 F^T F + 2 gamma L) with the band kernels (N = 1).
-double lipschitz_power(pdt_problem_s* pb, Instance& I, int iters) {
+// Power iteration for lambda_max(W^(1/2) (2 F^T F + 2 gamma L) W^(1/2)) with the band
+// kernels (N = 1); W = diag(wrow), or the identity when wrow is null.
+double lipschitz_power(pdt_problem_s* pb, Instance& I, int iters, const double* wrow = nullptr) {
   Arena tmp;
   hipStream_t s = pb->stream;
   ProbView pv = view_of(I);
@@ -260,7 +268,7 @@ double lipschitz_power(pdt_problem_s* pb, Instance& I, int iters) {
     HIPCHK(hipMemsetAsync(Pz, 0, od * sizeof(double), s));
     std::vector<double> v0(xm, 0.0);
     const double inv = 1.0 / std::sqrt((double)I.M);
-    for (int64_t m = 0; m < I.M; ++m) v0[(size_t)m * 16] = inv;
+    for (int64_t m = 0; m < I.M; ++m) v0[(size_t)m * 16] = wrow ? std::sqrt(I.wrow_h[(size_t)m]) * inv : inv;
     HIPCHK(hipMemcpyAsync(w.X[0], v0.data(), xm * sizeof(double), hipMemcpyHostToDevice, s));
     SolverState s0;
     std::memset(&s0, 0, sizeof(s0));
@@ -269,7 +277,7 @@ double lipschitz_power(pdt_problem_s* pb, Instance& I, int iters) {
     for (int it = 0; it < iters; ++it) {
       HIPCHK(launch_fx<double>(pv, b, st, FX_EVAL, s));
       HIPCHK(launch_ftr<double>(pv, b, st, FTR_GRAD, 0.0, s));
-      HIPCHK(launch_power_normalize(w.G, w.X[0], (int)I.M, 16, lam, s));
+      HIPCHK(launch_power_normalize(w.G, w.X[0], (int)I.M, 16, wrow, lam, s));
     }
     double lam_h = 0;
     HIPCHK(hipMemcpyAsync(&lam_h, lam, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -372,8 +380,27 @@ void setup_instance(pdt_problem_s* pb, Instance& I, const pdt_problem_desc& d) {
   I.st = A.alloc<SolverState>(1);
   I.st_eval = A.alloc<SolverState>(1);
   I.scalar = A.alloc<double>(4);
+  // Hessian diagonal and the row weights of the scaled step (floored at 1e-12 max h so
+  // that rows no probe sees keep a finite step)
+  I.hdiag = A.alloc<double>(M);
+  I.wrow = A.alloc<double>(M);
+  HIPCHK(launch_setup_hdiag(view_of(I), I.hdiag, s));
+  I.hdiag_h.resize(M);
+  I.wrow_h.resize(M);
+  HIPCHK(hipMemcpyAsync(I.hdiag_h.data(), I.hdiag, M * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double hmax = 0.0;
+  for (double h : I.hdiag_h) hmax = std::max(hmax, h);
+  for (size_t m = 0; m < M; ++m) I.wrow_h[m] = hmax > 0.0 ? 1.0 / std::max(I.hdiag_h[m], 1e-12 * hmax) : 1.0;
+  HIPCHK(hipMemcpyAsync(I.wrow, I.wrow_h.data(), M * sizeof(double), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   I.L_hat = lipschitz_power(pb, I, 100);
+}
+
+// Lipschitz constant of the row-scaled step, computed on first use.
+double scaled_lipschitz(pdt_problem_s* pb, Instance& I) {
+  if (I.L_w <= 0.0) I.L_w = lipschitz_power(pb, I, 100, I.wrow);
+  return I.L_w;
 }
 
 template <typename T>
@@ -454,7 +481,8 @@ void drop_graphs(Instance& I) {
 // forward product of the current iterate that removes the drift of those updates.
 template <typename TS, typename TC>
 hipGraphExec_t get_graph(pdt_problem_s* pb, Instance& I, int var, const Bufs<TS>& b, double step) {
-  if (I.graph[var] && I.graph_step[var] == step && I.graph_hist[var] == b.history) return I.graph[var];
+  if (I.graph[var] && I.graph_step[var] == step && I.graph_hist[var] == b.history && I.graph_w[var] == b.wrow)
+    return I.graph[var];
   if (I.graph[var]) (void)hipGraphExecDestroy(I.graph[var]);
   I.graph[var] = nullptr;
   // recorded on the library's own stream (the caller's may be the legacy default
@@ -480,6 +508,7 @@ hipGraphExec_t get_graph(pdt_problem_s* pb, Instance& I, int var, const Bufs<TS>
   I.graph[var] = ge;
   I.graph_step[var] = step;
   I.graph_hist[var] = b.history;
+  I.graph_w[var] = b.wrow;
   return ge;
 }
 
@@ -511,11 +540,12 @@ SolverState run_chunks(pdt_problem_s* pb, Instance& I, int var, const Bufs<TS>& 
 }
 
 template <typename T>
-void run_loop(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double step, int var, SolverState& out) {
+void run_loop(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double step, const double* wrow, int var,
+              SolverState& out) {
   hipStream_t s = pb->stream;
   const ProbView pv = view_of(I);
   Work<T>& w = work_of<T>(I);
-  Bufs<T> b = bufs_of(I, w, o.history);
+  Bufs<T> b = bufs_of(I, w, o.history, wrow);
   HIPCHK(launch_fx<T>(pv, b, I.st, FX_INIT, s));
   HIPCHK(launch_decide(I.partials, fx_num_waves(pv), I.st, nullptr, DEC_INIT, s));
   out = run_chunks<T, T>(pb, I, var, b, step, o.max_iters, false);
@@ -523,11 +553,11 @@ void run_loop(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double st
 
 // Mixed path: FP32 products on FP64 iterates until progress stalls, then the FP64
 // refinement continues from the same state to the requested tolerance.
-void run_mixed(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double step, SolverState& out,
-               int64_t& refine_iters) {
+void run_mixed(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double step, const double* wrow,
+               SolverState& out, int64_t& refine_iters) {
   hipStream_t s = pb->stream;
   const ProbView pv = view_of(I);
-  Bufs<double> b = bufs_of(I, I.w64, o.history);
+  Bufs<double> b = bufs_of(I, I.w64, o.history, wrow);
   HIPCHK(launch_fx<double>(pv, b, I.st, FX_INIT, s));
   HIPCHK(launch_decide(I.partials, fx_num_waves(pv), I.st, nullptr, DEC_INIT, s));
   SolverState h = run_chunks<double, float>(pb, I, VAR_MIXED, b, step, o.max_iters, true);
@@ -626,6 +656,18 @@ pdt_status pdt_problem_bands(pdt_problem_t pb, int32_t* lo, int32_t* hi, double*
   return PDT_OK;
 }
 
+pdt_status pdt_problem_scaling(pdt_problem_t pb, double* hdiag, double* lipschitz_scaled) {
+  if (!pb) return set_err(PDT_ERR_INVALID_ARG, "problem is NULL");
+  try {
+    Instance& I = pb->inst[0];
+    if (hdiag) std::memcpy(hdiag, I.hdiag_h.data(), I.hdiag_h.size() * sizeof(double));
+    if (lipschitz_scaled) *lipschitz_scaled = scaled_lipschitz(pb, I);
+    return PDT_OK;
+  } catch (...) {
+    return status_of_current_exception();
+  }
+}
+
 static pdt_status objective_impl(pdt_problem_t pb, const double* Pi, double* f_out, double* grad_out,
                                  double* kkt_out) {
   if (!pb || !Pi) return set_err(PDT_ERR_INVALID_ARG, "problem and Pi must not be NULL");
@@ -670,6 +712,7 @@ pdt_status pdt_solve(pdt_problem_t pb, double* Pi, const pdt_solve_opts* opts, p
     return set_err(PDT_ERR_INVALID_ARG, "precision not supported");
   if (!std::isfinite(o.rel_obj_tol) || o.rel_obj_tol < 0 || !std::isfinite(o.f_star))
     return set_err(PDT_ERR_INVALID_ARG, "bad tolerance");
+  if (o.scaling != PDT_STEP_UNIFORM && o.scaling != PDT_STEP_DIAG) return set_err(PDT_ERR_INVALID_ARG, "bad scaling");
   const auto t0 = std::chrono::steady_clock::now();
   try {
     Instance& I = pb->inst[0];
@@ -677,8 +720,10 @@ pdt_status pdt_solve(pdt_problem_t pb, double* Pi, const pdt_solve_opts* opts, p
     Arena& A = pb->arena;
     ensure_work<double>(A, I, I.w64, I.P64);
     const size_t Np = (size_t)I.Npad, N = (size_t)I.N, M = (size_t)I.M;
-    const double L = o.step_L > 0 ? o.step_L : I.L_hat;
+    const bool scaled = o.scaling == PDT_STEP_DIAG;
+    const double L = o.step_L > 0 ? o.step_L : (scaled ? scaled_lipschitz(pb, I) : I.L_hat);
     const double step = 1.0 / L;
+    const double* wrow = scaled ? I.wrow : nullptr;
     // starting point in X64[0]: 1/N, or the caller's Pi projected onto the constraints
     if (o.init == PDT_INIT_USER) {
       HIPCHK(launch_project_rows<double>(Pi, I.w64.X[0], (long long)M, (int)N, (int)N, (int)Np, s));
@@ -694,8 +739,8 @@ pdt_status pdt_solve(pdt_problem_t pb, double* Pi, const pdt_solve_opts* opts, p
     SolverState fin;
     int64_t refine_iters = 0;
     if (o.precision == PDT_FP64 || o.precision == PDT_MIXED) {
-      if (o.precision == PDT_FP64) run_loop<double>(pb, I, o, step, VAR_FP64, fin);
-      else run_mixed(pb, I, o, step, fin, refine_iters);
+      if (o.precision == PDT_FP64) run_loop<double>(pb, I, o, step, wrow, VAR_FP64, fin);
+      else run_mixed(pb, I, o, step, wrow, fin, refine_iters);
       if (fin.ix_cur != 0)
         HIPCHK(hipMemcpyAsync(I.w64.X[0], I.w64.X[fin.ix_cur], M * Np * sizeof(double), hipMemcpyDeviceToDevice, s));
     } else {
@@ -705,7 +750,7 @@ pdt_status pdt_solve(pdt_problem_t pb, double* Pi, const pdt_solve_opts* opts, p
       }
       ensure_work<float>(A, I, I.w32, I.P32);
       HIPCHK(launch_convert_pad<double, float>(I.w64.X[0], I.w32.X[0], (long long)M, (int)Np, (int)Np, (int)Np, s));
-      run_loop<float>(pb, I, o, step, VAR_FP32, fin);
+      run_loop<float>(pb, I, o, step, wrow, VAR_FP32, fin);
       HIPCHK(launch_convert_pad<float, double>(I.w32.X[fin.ix_cur], I.w64.X[0], (long long)M, (int)Np, (int)Np,
                                                (int)Np, s));
     }
@@ -1077,9 +1122,9 @@ int learned_start(pdt_problem_s* pb, Instance& I, pdt_model_s* md) {
 namespace {
 
 template <typename T>
-void build_plan(pdt_problem_s* pb, int prec, const std::vector<double>& steps) {
+void build_plan(pdt_problem_s* pb, int prec, int scaling, const std::vector<double>& steps) {
   BatchPlan& P = pb->plan;
-  if (P.prec == prec && P.steps == steps) return;
+  if (P.prec == prec && P.scaling == scaling && P.steps == steps) return;
   if (P.graph) (void)hipGraphExecDestroy(P.graph);
   P = BatchPlan();
   pb->plan_arena.release();
@@ -1092,7 +1137,7 @@ void build_plan(pdt_problem_s* pb, int prec, const std::vector<double>& steps) {
     Instance& I = pb->inst[k];
     BatchInst<T> bi;
     bi.pv = view_of(I);
-    bi.b = bufs_of(I, work_of<T>(I), nullptr);
+    bi.b = bufs_of(I, work_of<T>(I), nullptr, scaling == PDT_STEP_DIAG ? I.wrow : nullptr);
     bi.st = I.st;
     bi.step = steps[k];
     bi.n_dt = fx_num_waves(bi.pv);
@@ -1133,6 +1178,7 @@ void build_plan(pdt_problem_s* pb, int prec, const std::vector<double>& steps) {
   }
   HIPCHK(hipStreamSynchronize(s));
   P.prec = prec;
+  P.scaling = scaling;
   P.steps = steps;
 }
 
@@ -1210,18 +1256,20 @@ pdt_status pdt_solve_batch(pdt_problem_t pb, double* const* Pi, const pdt_solve_
   if (o.precision != PDT_FP64 && o.precision != PDT_FP32) return set_err(PDT_ERR_INVALID_ARG, "batch precision must be FP64 or FP32");
   if (o.init != PDT_INIT_UNIFORM && o.init != PDT_INIT_USER) return set_err(PDT_ERR_INVALID_ARG, "bad init");
   if (o.history) return set_err(PDT_ERR_INVALID_ARG, "history is not supported for batches");
+  if (o.scaling != PDT_STEP_UNIFORM && o.scaling != PDT_STEP_DIAG) return set_err(PDT_ERR_INVALID_ARG, "bad scaling");
   for (size_t k = 0; k < n; ++k)
     if (!Pi[k]) return set_err(PDT_ERR_INVALID_ARG, "Pi[k] must not be NULL");
   const auto t0 = std::chrono::steady_clock::now();
   try {
     hipStream_t s = pb->stream;
     Arena& A = pb->arena;
-    std::vector<double> steps(n);
+    std::vector<double> steps(n), Ls(n);
     for (size_t k = 0; k < n; ++k) {
       Instance& I = pb->inst[k];
       ensure_work<double>(A, I, I.w64, I.P64);
       const size_t Np = (size_t)I.Npad, N = (size_t)I.N, M = (size_t)I.M;
-      steps[k] = 1.0 / (o.step_L > 0 ? o.step_L : I.L_hat);
+      Ls[k] = o.step_L > 0 ? o.step_L : (o.scaling == PDT_STEP_DIAG ? scaled_lipschitz(pb, I) : I.L_hat);
+      steps[k] = 1.0 / Ls[k];
       if (o.init == PDT_INIT_USER) HIPCHK(launch_project_rows<double>(Pi[k], I.w64.X[0], (long long)M, (int)N, (int)N, (int)Np, s));
       else HIPCHK(launch_fill_rows<double>(I.w64.X[0], (long long)M, (int)N, (int)Np, 1.0 / (double)N, s));
       const double fs = (f_star && f_star[k] > 0) ? f_star[k] : 0.0;
@@ -1237,10 +1285,10 @@ pdt_status pdt_solve_batch(pdt_problem_t pb, double* const* Pi, const pdt_solve_
     }
     std::vector<SolverState> fin;
     if (o.precision == PDT_FP64) {
-      build_plan<double>(pb, PDT_FP64, steps);
+      build_plan<double>(pb, PDT_FP64, o.scaling, steps);
       run_batch<double>(pb, o, PDT_FP64, fin);
     } else {
-      build_plan<float>(pb, PDT_FP32, steps);
+      build_plan<float>(pb, PDT_FP32, o.scaling, steps);
       run_batch<float>(pb, o, PDT_FP32, fin);
     }
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1267,7 +1315,7 @@ pdt_status pdt_solve_batch(pdt_problem_t pb, double* const* Pi, const pdt_solve_
         info[k].rejects = fin[k].rejects;
         info[k].objective = f;
         info[k].kkt = kkt;
-        info[k].L_used = 1.0 / steps[k];
+        info[k].L_used = Ls[k];
         info[k].seconds = secs;
         info[k].converged = conv ? 1 : 0;
         info[k].refine_iters = 0;

@@ -457,7 +457,8 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
     const T* __restrict__ Xc = b.X[st->ix_cur];
     const T* __restrict__ Xp = b.X[st->ix_prev];
     T* __restrict__ Xn = b.X[st->ix_new];
-    const T stp = (T)step;
+    // row-scaled step: this group's row takes step * w_m
+    const T stp = (T)((b.wrow && mval) ? step * b.wrow[m] : step);
     T z[1][NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
@@ -763,19 +764,38 @@ __global__ __launch_bounds__(64) void project_rows_kernel(const T* X, T* Y, long
   }
 }
 
-// power iteration: lambda = ||G[:,0]||, V[:,0] = G[:,0] / lambda
+// power iteration on W^(1/2) H W^(1/2) with the iterate kept as u = W^(1/2) v:
+// lambda = sqrt(sum_m w_m G_m^2), V_m = w_m G_m / lambda (w = null: all ones)
 __global__ __launch_bounds__(256) void power_normalize_kernel(const double* G, double* V, int M, int ld,
-                                                              double* lam_out) {
+                                                              const double* w, double* lam_out) {
   __shared__ double sh[256];
   double s = 0.0;
   for (int m = threadIdx.x; m < M; m += 256) {
     const double g = G[(size_t)m * ld];
-    s += g * g;
+    s += (w ? w[m] : 1.0) * g * g;
   }
   const double lam = sqrt(block_sum256(s, sh));
   const double inv = lam > 0.0 ? 1.0 / lam : 0.0;
-  for (int m = threadIdx.x; m < M; m += 256) V[(size_t)m * ld] = G[(size_t)m * ld] * inv;
+  for (int m = threadIdx.x; m < M; m += 256) V[(size_t)m * ld] = (w ? w[m] : 1.0) * G[(size_t)m * ld] * inv;
   if (threadIdx.x == 0) *lam_out = lam;
+}
+
+// Hessian diagonal of row m: 2 sum_d F[d][m]^2 over the probes whose band holds m (FP64
+// Loader values, summed in increasing d), plus 2 gamma L[m][m] (1 at the ends, 2 inside).
+__global__ __launch_bounds__(256) void setup_hdiag_kernel(ProbView pv, double* hdiag) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= pv.M) return;
+  const int t = m >> 4;
+  const int dlo = pv.mt_dlo[t], dhi = pv.mt_dhi[t];
+  const bool lumped = pv.lump && m == pv.M - 1;
+  double s = 0.0;
+  for (int d = dlo; d <= dhi; ++d) {
+    if (m < pv.lo[d] || m > pv.hi[d]) continue;
+    const double v = lumped ? pv.tail[d] : poisson_pmf(m, pv.mu[d]);
+    s += v * v;
+  }
+  const double ld = pv.M < 2 ? 0.0 : ((m == 0 || m == pv.M - 1) ? 1.0 : 2.0);
+  hdiag[m] = 2.0 * s + 2.0 * pv.gamma * ld;
 }
 
 template <typename T>
@@ -938,8 +958,15 @@ hipError_t launch_project_rows(const T* X, T* Y, long long rows, int cols, int l
   return hipGetLastError();
 }
 
-hipError_t launch_power_normalize(double* G, double* V, int M, int ld, double* lam_out, hipStream_t s) {
-  hipLaunchKernelGGL(power_normalize_kernel, dim3(1), dim3(256), 0, s, G, V, M, ld, lam_out);
+hipError_t launch_power_normalize(double* G, double* V, int M, int ld, const double* w, double* lam_out,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(power_normalize_kernel, dim3(1), dim3(256), 0, s, G, V, M, ld, w, lam_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_setup_hdiag(const ProbView& pv, double* hdiag, hipStream_t s) {
+  if (pv.M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(setup_hdiag_kernel, dim3((pv.M + 255) / 256), dim3(256), 0, s, pv, hdiag);
   return hipGetLastError();
 }
 

@@ -6,8 +6,9 @@ D = round(1.2 M) probes with mu linearly spaced to 1.1 M; 1e7 shots per probe;
 gamma = 1e-4.  Training and test detectors come from disjoint seed streams.
 
 Protocol per test detector: the cold FP64 solve, the warm FP64 solve and the warm mixed
-solve each run K iterations with the objective recorded after every iteration; the
-reference optimum is the lowest objective any of them reached.  Iterations to a relative
+solve (all with the row-scaled step), and the cold FP64 solve with the uniform step 1/L,
+each run K iterations with the objective recorded after every iteration; the reference
+optimum is the lowest objective any of them reached.  Iterations to a relative
 objective tol are read from the histories; times are iterations x the run's measured
 time per iteration, plus the measured cost of the learned start for warm runs.
 
@@ -93,14 +94,18 @@ def main(argv=None):
     for inst in test:
         pb = _pdt.Problem.from_instance(inst)
         runs = {}
-        for name, init, prec in (("cold_fp64", _pdt.PDT_INIT_UNIFORM, _pdt.PDT_FP64),
-                                 ("warm_fp64", _pdt.PDT_INIT_LEARNED, _pdt.PDT_FP64),
-                                 ("warm_mixed", _pdt.PDT_INIT_LEARNED, _pdt.PDT_MIXED)):
+        DIAG, UNIFORM = _pdt.PDT_STEP_DIAG, _pdt.PDT_STEP_UNIFORM
+        # the scaled step's Lipschitz constant is set up once per problem, outside the timings
+        pb.solve(torch.zeros((inst.M, inst.N), dtype=torch.float64, device="cuda"), max_iters=0, scaling=DIAG)
+        for name, init, prec, sc in (("cold_fp64", _pdt.PDT_INIT_UNIFORM, _pdt.PDT_FP64, DIAG),
+                                     ("warm_fp64", _pdt.PDT_INIT_LEARNED, _pdt.PDT_FP64, DIAG),
+                                     ("warm_mixed", _pdt.PDT_INIT_LEARNED, _pdt.PDT_MIXED, DIAG),
+                                     ("cold_fp64_uniform", _pdt.PDT_INIT_UNIFORM, _pdt.PDT_FP64, UNIFORM)):
             Pi = torch.zeros((inst.M, inst.N), dtype=torch.float64, device="cuda")
             h = torch.zeros(args.K, dtype=torch.float64, device="cuda")
             torch.cuda.synchronize()
             t = time.time()
-            info = pb.solve(Pi, init=init, precision=prec, max_iters=args.K, history=h,
+            info = pb.solve(Pi, init=init, precision=prec, max_iters=args.K, history=h, scaling=sc,
                             model=model if init == _pdt.PDT_INIT_LEARNED else None)
             torch.cuda.synchronize()
             wall = time.time() - t
@@ -122,11 +127,12 @@ def main(argv=None):
                "f_start_cold": c0["objective"], "f_start_warm": f0["objective"],
                "fell_back": f0["fell_back_to_cold"], "learned_start_s": t_init - t_cold0}
         for name, r in runs.items():
-            per_it = (r["wall"] - (t_cold0 if name == "cold_fp64" else t_init)) / args.K
+            cold = name.startswith("cold")
+            per_it = (r["wall"] - (t_cold0 if cold else t_init)) / args.K
             row[name] = {"s_per_iter": per_it, "wall": r["wall"], "final_relobj": (float(r["hist"][-1]) - fref) / fref}
             for tol in (1e-4, 1e-6, 1e-8):
                 k = iters_to(r["hist"], fref, tol)
-                extra = 0.0 if name == "cold_fp64" else row["learned_start_s"]
+                extra = 0.0 if cold else row["learned_start_s"]
                 row[name][f"iters_{tol:g}"] = k
                 row[name][f"time_{tol:g}"] = None if k is None else k * per_it + extra
         log(f"[ws] test bins={row['bins']}: " + ", ".join(
@@ -144,7 +150,12 @@ def main(argv=None):
                "epochs": args.epochs, "hidden": args.hidden, "train_loss": [hist[0], hist[-1]],
                "t_targets_s": t_targets, "t_train_s": t_train, "K": args.K, "tests": results}
     for tol in (1e-4, 1e-6, 1e-8):
-        summary[f"median_time_{tol:g}"] = {k: med(k, tol) for k in ("cold_fp64", "warm_fp64", "warm_mixed")}
+        summary[f"median_time_{tol:g}"] = {k: med(k, tol) for k in ("cold_fp64", "warm_fp64", "warm_mixed",
+                                                                    "cold_fp64_uniform")}
+        summary[f"median_iters_{tol:g}"] = {
+            k: (float(np.median([r[k][f"iters_{tol:g}"] for r in results if r[k][f"iters_{tol:g}"] is not None]))
+                if any(r[k][f"iters_{tol:g}"] is not None for r in results) else None)
+            for k in ("cold_fp64", "warm_fp64", "warm_mixed", "cold_fp64_uniform")}
     log(json.dumps({k: v for k, v in summary.items() if k != "tests"}, indent=1))
     if args.out:
         with open(args.out, "w") as fh:

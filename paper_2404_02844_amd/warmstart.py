@@ -26,7 +26,7 @@ class Pair:
 
 
 def solve_pair(inst, *, max_iters: int, precision=_pdt.PDT_MIXED, start_from_truth: bool = True,
-               rel_tol: float = 0.0, f_star: float = 0.0) -> Pair:
+               rel_tol: float = 0.0, f_star: float = 0.0, scaling: int = _pdt.PDT_STEP_DIAG) -> Pair:
     """Solve one training detector and return its (features, Pi* columns) pair.
 
     Starting from the generating POVM (known for synthetic detectors) only shortens the
@@ -36,7 +36,7 @@ def solve_pair(inst, *, max_iters: int, precision=_pdt.PDT_MIXED, start_from_tru
     Pi = torch.as_tensor(inst.Pi_true if start_from_truth else np.zeros((inst.M, inst.N)),
                          dtype=torch.float64, device="cuda").contiguous()
     info = pb.solve(Pi, precision=precision, init=_pdt.PDT_INIT_USER if start_from_truth else _pdt.PDT_INIT_UNIFORM,
-                    max_iters=max_iters, rel_obj_tol=rel_tol, f_star=f_star)
+                    max_iters=max_iters, rel_obj_tol=rel_tol, f_star=f_star, scaling=scaling)
     bins = inst.detector["B"]
     X = torch.empty((bins + 1, N_IN), dtype=torch.float32, device="cuda")
     got = _pdt.pdt_warmstart_features(pb.handle, X)

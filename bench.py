@@ -84,8 +84,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-9)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4"],
-                    help="c2: M=4096 N=65 D=5000 to tolerance (default); c4: 256-detector batch")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"],
+                    help="c2: M=4096 N=65 D=5000 to tolerance (default); c3: M=1e6 N=100 D=1e5, "
+                         "fixed iterations; c4: 256-detector batch")
     ap.add_argument("--kernels-only", action="store_true",
                     help="short run for profilers: 200 iterations, then 200 launches of each kernel")
     args = ap.parse_args()
@@ -100,6 +101,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "c4":
         return bench_batch(args)
+    if args.workload == "c3":
+        return bench_mega(args)
     inst = synth.c2_medium()
     M, N, D = inst.M, inst.N, inst.D
     log(f"[bench] workload {inst.name}: M={M} N={N} D={D}")
@@ -275,6 +278,77 @@ def bench_batch(args, count=256, iters=2000):
                    "step": "row-scaled (Hessian diagonal)"},
         "instances_per_s": count / el,
         "objective_range": [min(i["objective"] for i in infos), max(i["objective"] for i in infos)],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def replay_time(pb, kern, prec, reps):
+    """Average launch time of one kernel of the iteration, from HIP events on the stream it
+    is launched on."""
+    import torch
+    from paper_2404_02844_amd import _pdt
+    stream = torch.cuda.current_stream()
+    _pdt.pdt_replay_kernel(pb.handle, kern, prec, 2)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    _pdt.pdt_replay_kernel(pb.handle, kern, prec, reps)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e-3
+
+
+def bench_mega(args, iters=64):
+    """M=1e6, N=100, D=1e5 (99-bin detector with 1% crosstalk, mu on [0, 1.1e6], 1e8 shots,
+    gamma 1e-5): a fixed number of FP64 and mixed-precision iterations with the row-scaled
+    step from Pi = 1/N, and the per-launch times of the band kernels at this size."""
+    import torch
+    from paper_2404_02844_amd import _pdt, synth
+    t0 = time.perf_counter()
+    inst = synth.c3_mega(workers=min(16, os.cpu_count() or 1))
+    log(f"[bench] generated {inst.name} in {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    pb = _pdt.Problem.from_instance(inst)
+    nnz = pb.bands()["nnz"]
+    Lw = pb.scaling()["lipschitz_scaled"]
+    log(f"[bench] setup {time.perf_counter() - t0:.1f} s, band entries {nnz:.4e}, L_w {Lw:.4e}")
+    M, N = inst.M, inst.N
+    Pi = torch.zeros((M, N), dtype=torch.float64, device="cuda")
+    res = {}
+    for name, prec in (("fp64", _pdt.PDT_FP64), ("mixed", _pdt.PDT_MIXED)):
+        for _ in range(args.warmup):
+            pb.solve(Pi, precision=prec, max_iters=iters, scaling=_pdt.PDT_STEP_DIAG)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            info = pb.solve(Pi, precision=prec, max_iters=iters, scaling=_pdt.PDT_STEP_DIAG)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t) / args.steps
+        res[name] = {"s_per_solve": el, "iters": iters, "f": info["objective"],
+                     "elem_iters_per_s": M * N * iters / el}
+        log(f"[bench] {name}: {iters} iterations in {el:.3f} s, f = {info['objective']:.6e}")
+    times = {}
+    for kern, name in ((0, "ftr"), (1, "fx"), (3, "iteration")):
+        times[name] = replay_time(pb, kern, _pdt.PDT_FP64, 20)
+        times["mixed_" + name] = replay_time(pb, kern, _pdt.PDT_MIXED, 20)
+    log("[bench] kernel times (ms): " + " ".join(f"{k}={v * 1e3:.3f}" for k, v in times.items()))
+    flops = 2.0 * nnz * N
+    achieved = flops / times["ftr"] / 1e12
+    out = {
+        "metric": METRIC, "value": res["fp64"]["elem_iters_per_s"], "unit": "POVM-elem*iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["fp64"]["s_per_solve"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": inst.name, "M": M, "N": N, "D": inst.D, "gamma": inst.gamma,
+                   "pmf_threshold": inst.threshold, "tail": "lump", "iters": iters, "band_entries": nnz,
+                   "step": "row-scaled (Hessian diagonal)"},
+        "mixed": res["mixed"],
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "ftr_kernel<double> (F^T R band product + projected step)",
+                     "per_launch_flops": flops, "avg_launch_s": times["ftr"], "fx_avg_launch_s": times["fx"],
+                     "iteration_s": times["iteration"],
+                     "mixed_ftr_tflops": flops / times["mixed_ftr"] / 1e12,
+                     "mixed_fx_tflops": flops / times["mixed_fx"] / 1e12},
+        "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 

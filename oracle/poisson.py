@@ -141,7 +141,11 @@ def band_edges(mu: float, M: int, tau: float, tail_mode: int) -> tuple[int, int]
     w_lo = max(0, int(math.floor(mu - 14.0 * sd - 60)))
     w_hi = min(M - 1, int(math.ceil(mu + 14.0 * sd + 60)))
     if w_lo > M - 1:
-        w_lo = M - 1
+        # every photon number below M-1 lies more than 14 sd under the mean: only the
+        # lumped last column can reach tau
+        if tail_mode == LUMP and upper_tail(mu, M - 1) >= tau:
+            return M - 1, M - 1
+        return 1, 0
     ms = np.arange(w_lo, w_hi + 1)
     vals = pmf(ms, mu)
     if tail_mode == LUMP and w_hi == M - 1:

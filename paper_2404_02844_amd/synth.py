@@ -118,13 +118,64 @@ def _probe_window(mu: float, lo_cap: int, hi_cap: int) -> tuple[int, int]:
     return max(lo, lo_cap), hi
 
 
-def outcome_probs(mu: np.ndarray, Pi_ext: np.ndarray, M: int, tail_mode: int) -> np.ndarray:
+_POOL_PI = None  # detector matrix inherited by forked generator processes
+
+
+def _outcome_chunk(args):
+    mu, M, tail_mode = args
+    return _outcome_rows_blocked(mu, _POOL_PI, M, tail_mode)
+
+
+def _outcome_rows_blocked(mu: np.ndarray, Pi_ext: np.ndarray, M: int, tail_mode: int, block: int = 64) -> np.ndarray:
+    """LUMP rows for blocks of consecutive probes: one pmf matrix over the union of their
+    windows and one matrix product per block, so Pi_true is streamed once per block."""
+    D = mu.shape[0]
+    N = Pi_ext.shape[1]
+    q = np.zeros((D, N))
+    for b0 in range(0, D, block):
+        b1 = min(D, b0 + block)
+        mus = mu[b0:b1].astype(np.float64)
+        los, his = zip(*(_probe_window(float(m_), 0, M - 2) for m_ in mus))
+        lo, hi = min(los), max(his)
+        if lo <= hi:
+            ms = np.arange(lo, hi + 1)
+            W = stats.poisson.pmf(ms[None, :], mus[:, None])
+            W[mus == 0.0] = 0.0
+            W[mus == 0.0, 0] = 1.0 if lo == 0 else 0.0
+            q[b0:b1] = W @ Pi_ext[lo:hi + 1]
+        q[b0:b1] += stats.poisson.sf(M - 2, mus)[:, None] * Pi_ext[M - 1][None, :]
+    return q
+
+
+def outcome_probs(mu: np.ndarray, Pi_ext: np.ndarray, M: int, tail_mode: int, workers: int = 1) -> np.ndarray:
     """q_d = sum_m Poisson(m; mu_d) Pi_true[m, :] (scipy pmf; data generation only).
 
     LUMP: rows m >= M-1 of the detector are represented by row M-1 (tail mass on it).
     TRUNCATE: Pi_ext must extend far enough past M that the Poisson tail is negligible;
-    the physical detector is defined for every photon number.
+    the physical detector is defined for every photon number.  workers > 1 (LUMP only)
+    splits the probes over forked processes and forms the rows of 64 consecutive probes
+    with one matrix product over their joint window (the same sums, another rounding
+    order).
     """
+    if workers <= 1 or mu.shape[0] < 4 * workers or tail_mode != LUMP:
+        q = _outcome_rows(mu, Pi_ext, M, tail_mode)
+    else:
+        import multiprocessing as mp
+        global _POOL_PI
+        _POOL_PI = Pi_ext
+        try:
+            # fixed 2048-probe chunks: the 64-probe blocks, and so the rounding, do not
+            # depend on the number of workers
+            chunks = [mu[k:k + 2048] for k in range(0, mu.shape[0], 2048)]
+            with mp.get_context("fork").Pool(workers) as pool:
+                q = np.concatenate(pool.map(_outcome_chunk, [(c, M, tail_mode) for c in chunks]), axis=0)
+        finally:
+            _POOL_PI = None
+    q = np.clip(q, 0.0, None)
+    return q / q.sum(axis=1, keepdims=True)
+
+
+def _outcome_rows(mu: np.ndarray, Pi_ext: np.ndarray, M: int, tail_mode: int) -> np.ndarray:
     D = mu.shape[0]
     N = Pi_ext.shape[1]
     q = np.zeros((D, N))
@@ -144,8 +195,7 @@ def outcome_probs(mu: np.ndarray, Pi_ext: np.ndarray, M: int, tail_mode: int) ->
             lo, hi = _probe_window(m_, 0, last)
             ms = np.arange(lo, hi + 1)
             q[d] = stats.poisson.pmf(ms, m_) @ Pi_ext[lo:hi + 1]
-    q = np.clip(q, 0.0, None)
-    return q / q.sum(axis=1, keepdims=True)
+    return q
 
 
 def sample_outcomes(q: np.ndarray, shots: float, rng: np.random.Generator) -> np.ndarray:
@@ -158,7 +208,7 @@ def make_instance(name: str, *, M: int, B: int, eta: float, D: int, mu_max: floa
                   shots: float, gamma: float, tail_mode: int, threshold: float,
                   dark: float = 0.0, crosstalk: float = 0.0,
                   rng: np.random.Generator, seed: int = 0, n_pad_to: Optional[int] = None,
-                  noiseless: bool = False) -> Instance:
+                  noiseless: bool = False, workers: int = 1) -> Instance:
     N = B + 1
     mu = np.linspace(0.0, mu_max, D)
     if tail_mode == TRUNCATE:
@@ -166,7 +216,7 @@ def make_instance(name: str, *, M: int, B: int, eta: float, D: int, mu_max: floa
         Pi_ext = click_detector_povm(max(M, ext + 1), B, eta, dark, crosstalk)
     else:
         Pi_ext = click_detector_povm(M, B, eta, dark, crosstalk)
-    q = outcome_probs(mu, Pi_ext, M, tail_mode)
+    q = outcome_probs(mu, Pi_ext, M, tail_mode, workers=workers)
     P = q.copy() if noiseless else sample_outcomes(q, shots, rng)
     Pi_true = Pi_ext[:M].copy()
     if n_pad_to is not None and n_pad_to > N:
@@ -195,11 +245,11 @@ def c2_medium(seed_offset: int = 0) -> Instance:
                          rng=rng_for(2 + seed_offset), seed=SEED_BASE + 2 + seed_offset)
 
 
-def c3_mega(M: int = 1_000_000, D: int = 100_000) -> Instance:
+def c3_mega(M: int = 1_000_000, D: int = 100_000, workers: int = 16) -> Instance:
     """99-bin detector with 1% crosstalk, M=1e6, N=100, D=1e5 probes on mu in [0, 1.1M]."""
     return make_instance(f"c3_m{M}_n100_d{D}", M=M, B=99, eta=0.8, crosstalk=0.01, D=D,
                          mu_max=1.1 * M, shots=1e8, gamma=1e-5, tail_mode=LUMP, threshold=1e-16,
-                         rng=rng_for(3), seed=SEED_BASE + 3)
+                         rng=rng_for(3), seed=SEED_BASE + 3, workers=workers)
 
 
 def random_detector(rng: np.random.Generator, M: int, *, bins=(8, 128), eta=(0.5, 0.95),

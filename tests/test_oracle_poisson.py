@@ -117,3 +117,13 @@ def test_band_edges_bracket_threshold(mu):
         assert val(lo - 1) < tau * (1 + 1e-12)
     if hi < M - 1:
         assert val(hi + 1) < tau * (1 + 1e-12)
+
+
+def test_band_of_a_probe_far_beyond_the_cutoff():
+    # mu more than 14 sd above M-1: only the lumped column holds mass (it is ~1)
+    M = 1000
+    lo, hi = poisson.band_edges(5000.0, M, 1e-16, poisson.LUMP)
+    assert (lo, hi) == (M - 1, M - 1)
+    assert poisson.upper_tail(5000.0, M - 1) == 1.0
+    lo, hi = poisson.band_edges(5000.0, M, 1e-16, poisson.TRUNCATE)
+    assert lo > hi

@@ -63,6 +63,7 @@ struct Arena {
 
 template <typename T>
 struct Work {
+  float* dX = nullptr;  // FP32 X_new - X_cur of the mixed path (FP64 storage only)
   T* X[3] = {nullptr, nullptr, nullptr};
   T* O[3] = {nullptr, nullptr, nullptr};
   T* R_acc = nullptr;
@@ -201,6 +202,7 @@ Bufs<T> bufs_of(const Instance& I, const Work<T>& w, double* history, const doub
   b.n_partials = I.n_partials;
   b.history = history;
   b.wrow = wrow;
+  b.dX = w.dX;
   return b;
 }
 
@@ -224,7 +226,9 @@ void validate_desc(const pdt_problem_desc& d) {
   if (d.N > 16 * kMaxNT) throw ArgError{"N must be <= " + std::to_string(16 * kMaxNT)};
   if (d.M > (int64_t)INT_MAX - 1024 || d.D > (int64_t)INT_MAX - 1024) throw ArgError{"M or D too large"};
   const int64_t npad = (d.N + 15) / 16 * 16;
-  if (d.M > (int64_t)1 << 40 || d.M * npad > ((int64_t)1 << 46)) throw ArgError{"M*N too large"};
+  // the kernels address [M][Npad] and [D][Npad] arrays with 32-bit offsets
+  if (d.M * npad > (int64_t)INT_MAX || d.D * npad > (int64_t)INT_MAX)
+    throw ArgError{"M*Npad and D*Npad must be < 2^31 (Npad = 16 * ceil(N / 16))"};
   if (!d.mu || !d.P) throw ArgError{"mu and P must not be NULL"};
   if (!std::isfinite(d.gamma) || d.gamma < 0) throw ArgError{"gamma must be finite and >= 0"};
   if (!std::isfinite(d.pmf_threshold) || d.pmf_threshold < 0 || d.pmf_threshold >= 1)
@@ -557,6 +561,11 @@ void run_mixed(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double s
                SolverState& out, int64_t& refine_iters) {
   hipStream_t s = pb->stream;
   const ProbView pv = view_of(I);
+  if (!I.w64.dX) {
+    const size_t xm = (size_t)I.M * I.Npad;
+    I.w64.dX = pb->arena.alloc<float>(xm);
+    HIPCHK(hipMemsetAsync(I.w64.dX, 0, xm * sizeof(float), s));
+  }
   Bufs<double> b = bufs_of(I, I.w64, o.history, wrow);
   HIPCHK(launch_fx<double>(pv, b, I.st, FX_INIT, s));
   HIPCHK(launch_decide(I.partials, fx_num_waves(pv), I.st, nullptr, DEC_INIT, s));
@@ -792,7 +801,7 @@ pdt_status pdt_replay_kernel(pdt_problem_t pb, int kernel, int precision, int64_
       if (!I.w32.ready) return set_err(PDT_ERR_INVALID_ARG, "solve in FP32 once before replaying");
       replay_impl<float>(pb, I, kernel, reps);
     } else if (precision == PDT_MIXED) {
-      if (!I.w64.ready) return set_err(PDT_ERR_INVALID_ARG, "solve once before replaying");
+      if (!I.w64.ready || !I.w64.dX) return set_err(PDT_ERR_INVALID_ARG, "solve in mixed precision once before replaying");
       replay_impl<double, float>(pb, I, kernel, reps);
     } else {
       return set_err(PDT_ERR_INVALID_ARG, "precision not supported");

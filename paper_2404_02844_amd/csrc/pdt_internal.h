@@ -14,6 +14,7 @@
 //   O[3]    [D][Npad]     F X for the three iterates
 //   R_acc, R_rej [D][Npad] residual F Y - P for the next step, if the candidate is
 //                         accepted / rejected (both formed before the decision)
+//   dX      [M][Npad]     FP32 candidate step X_new - X_cur (mixed path only)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -81,6 +82,8 @@ struct Bufs {
   int n_partials;
   double* history;   // f after every iteration (may be null)
   const double* wrow = nullptr;  // [M] per-row step weights (null: every row takes the step)
+  float* dX = nullptr;           // [M][Npad] FP32 X_new - X_cur (mixed path: written by the
+                                 // transposed product, read by the forward product)
 };
 
 // One instance of a batched launch: its problem view, buffers, state and step; n_dt

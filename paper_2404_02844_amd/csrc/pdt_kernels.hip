@@ -203,7 +203,6 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
   const int ix_cur = st->ix_cur;
   const int ix_x = iter ? st->ix_new : ix_cur;
   const T* __restrict__ X = b.X[ix_x];
-  const T* __restrict__ Xcur = b.X[ix_cur];
   T* __restrict__ O = b.O[ix_x];
   const T* __restrict__ Ocur = b.O[ix_cur];
   // the mixed instantiation (float products on double storage) always forms the delta
@@ -233,8 +232,9 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
     const int m = mrow < M - 1 ? mrow : M - 1;
     const unsigned base = (unsigned)m * (unsigned)Npad + (unsigned)i;
     if constexpr (delta) {
+      // the candidate step, written in FP32 by the transposed product's epilogue
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) dst[nt] = (TC)(X[base + 16u * nt] - Xcur[base + 16u * nt]);
+      for (int nt = 0; nt < NT; ++nt) dst[nt] = (TC)b.dX[base + 16u * nt];
     } else {
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) dst[nt] = (TC)X[base + 16u * nt];
@@ -459,14 +459,19 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
     T* __restrict__ Xn = b.X[st->ix_new];
     // row-scaled step: this group's row takes step * w_m
     const T stp = (T)((b.wrow && mval) ? step * b.wrow[m] : step);
+    // the mixed instantiation also hands the forward product the step X_new - X_cur in FP32
+    constexpr bool delta = !std::is_same<TS, TC>::value;
     T z[1][NT];
+    T xcs[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const int n = nt * 16 + i;
       T zz = (n < N) ? (T)0 : neg_huge<T>();
+      xcs[nt] = 0;
       if (mval && n < N) {
         const size_t off = (size_t)m * Npad + n;
         const T xc = Xc[off];
+        xcs[nt] = xc;
         const T y = xc + beta * (xc - Xp[off]);
         T ly = 0;
         if (m > 0) {
@@ -488,7 +493,9 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         const int n = nt * 16 + i;
-        Xn[(size_t)m * Npad + n] = (n < N) ? fmax(z[0][nt] - tau[0], (T)0) : (T)0;
+        const T xn = (n < N) ? fmax(z[0][nt] - tau[0], (T)0) : (T)0;
+        Xn[(size_t)m * Npad + n] = xn;
+        if constexpr (delta) b.dX[(size_t)m * Npad + n] = (float)(xn - xcs[nt]);
       }
     }
   } else {

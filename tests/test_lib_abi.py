@@ -46,6 +46,7 @@ def _desc_call(**over):
     (dict(pmf_threshold=1.5), "pmf_threshold"),
     (dict(tail_mode=7), "tail_mode"),
     (dict(P=np.full((6, 300), 1 / 300)), "N must be"),
+    (dict(M=200_000_000), "2^31"),
 ])
 def test_invalid_arguments_are_rejected(over, msg):
     with pytest.raises(_pdt.PdtError) as ei:

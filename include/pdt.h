@@ -192,6 +192,19 @@ pdt_status pdt_problem_bands(pdt_problem_t problem, int32_t* lo, int32_t* hi, do
 pdt_status pdt_problem_scaling(pdt_problem_t problem, double* hdiag, double* lipschitz_scaled);
 
 /*
+ * Workgroup shape of the two band kernels (not a quantity of the paper: a launch
+ * parameter).  Each band product runs one workgroup per 16-row tile whose waves split
+ * the tile's contraction; ks_fx / ks_ftr waves (4 or 8) for the forward / transposed
+ * product of the given precision of one instance.  0 selects the tuning table, which
+ * picks 8 for launches with few tiles (see pdt_tuning.h).  The waves' partial results
+ * are summed in a fixed order, so a given shape is deterministic, while the two shapes
+ * differ in rounding.  Changing the shape drops captured graphs and the batch plan.
+ */
+pdt_status pdt_problem_set_tiles(pdt_problem_t problem, int64_t instance, int precision, int ks_fx, int ks_ftr);
+/* The shape in effect (host int* outputs, nullable). */
+pdt_status pdt_problem_tiles(pdt_problem_t problem, int64_t instance, int precision, int* ks_fx, int* ks_ftr);
+
+/*
  * Warm-start network (learned initial Pi; not in the paper, whose runs start from
  * Pi = 1/N and, for its smoothed second run, from a window average of a solution).
  * Four linear layers n_in -> hidden -> hidden -> hidden -> n_out with the tanh form of

@@ -86,6 +86,8 @@ def lib() -> ctypes.CDLL:
         L.pdt_problem_bands.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), dp, dp,
                                         ctypes.POINTER(ctypes.c_int64)]
         L.pdt_problem_scaling.argtypes = [vp, dp, dp]
+        L.pdt_problem_set_tiles.argtypes = [vp, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.pdt_problem_tiles.argtypes = [vp, i64, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         L.pdt_replay_kernel.argtypes = [vp, ctypes.c_int, ctypes.c_int, i64]
         L.pdt_replay_kernel.restype = ctypes.c_int
         L.pdt_model_create.argtypes = [i64, i64, i64, vp, vp, ctypes.POINTER(vp)]
@@ -107,7 +109,8 @@ def lib() -> ctypes.CDLL:
         L.pdt_last_error.argtypes = []
         L.pdt_last_error.restype = ctypes.c_char_p
         for name in ("pdt_make_problem", "pdt_solve", "pdt_objective", "pdt_kkt", "pdt_project_simplex",
-                     "pdt_project_simplex_f32", "pdt_problem_bands", "pdt_problem_scaling"):
+                     "pdt_project_simplex_f32", "pdt_problem_bands", "pdt_problem_scaling",
+                     "pdt_problem_set_tiles", "pdt_problem_tiles"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -237,6 +240,16 @@ def pdt_problem_scaling(handle, M: int) -> dict:
     return {"hdiag": h, "lipschitz_scaled": Lw.value}
 
 
+def pdt_problem_set_tiles(handle, instance: int, precision: int, ks_fx: int, ks_ftr: int) -> None:
+    _check(lib().pdt_problem_set_tiles(handle, int(instance), int(precision), int(ks_fx), int(ks_ftr)))
+
+
+def pdt_problem_tiles(handle, instance: int, precision: int) -> tuple:
+    a, b = ctypes.c_int(), ctypes.c_int()
+    _check(lib().pdt_problem_tiles(handle, int(instance), int(precision), ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
 class Problem:
     """Owns a problem handle; thin convenience over the pdt_* calls."""
 
@@ -264,6 +277,12 @@ class Problem:
 
     def scaling(self):
         return pdt_problem_scaling(self.handle, self.M)
+
+    def set_tiles(self, precision, ks_fx, ks_ftr):
+        pdt_problem_set_tiles(self.handle, 0, precision, ks_fx, ks_ftr)
+
+    def tiles(self, precision):
+        return pdt_problem_tiles(self.handle, 0, precision)
 
     def close(self):
         if self.handle:

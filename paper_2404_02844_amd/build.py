@@ -7,13 +7,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdt.so")
-SOURCES = ["pdt_kernels.hip", "pdt_mlp.hip", "pdt_capi.hip"]
+SOURCES = ["pdt_band_f64.hip", "pdt_band_f32.hip", "pdt_band_mixed.hip", "pdt_band_batch.hip",
+           "pdt_kernels.hip", "pdt_mlp.hip", "pdt_capi.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # keep packed FP32 instructions out of every kernel
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False) -> str:
     """Compile every source to an object in parallel, then link the shared library."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objdir = os.path.join(HERE, "_build")

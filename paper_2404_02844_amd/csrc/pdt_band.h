@@ -1,0 +1,603 @@
+// Band-GEMM kernels of the projected-gradient detector-tomography solver (gfx950).
+//
+// The two products of every iteration are banded: F[d][m] is non-negligible only for
+// m in [lo_d, hi_d] (Sec. 3.2, Data distribution), and F is never stored -- each
+// kernel regenerates its F tile in registers from one FP64 anchor per 16 entries and
+// the ratio recursion p(m+1) = p(m) mu / (m+1).
+//
+//   fx_kernel   O = F X over a 16-probe tile (MFMA 16x16x4, A = F tile, B = X rows),
+//               epilogue: ||O - P||^2 partial, residuals for the next step, and the
+//               nearest-neighbour regulariser (Eq. regul) over a slice of rows.
+//   ftr_kernel  G = 2 F^T R + 2 gamma L Y over a 16-row tile of Pi (MFMA, A = F^T tile
+//               staged through LDS, B = R rows); epilogue: gradient step, row-wise
+//               Euclidean projection onto the simplex (Eq. Mp1_proj), write X_{k+1}.
+//   decide      fixed-order FP64 reduction of the per-wave partials, accept/reject and
+//               the momentum scalars.
+//
+// MFMA lane layout (v_mfma_{f64,f32}_16x16x4, measured on gfx950): lane l holds
+// A[l%16][l/16] and B[l/16][l%16]; the result register r of lane l is C[row][l%16] with
+// row = 4*(l/16) + r for FP32 but row = l/16 + 4*r for FP64.  The contraction index
+// k = l/16 is mapped to whichever photon number / probe keeps the lane's F values
+// consecutive.
+//
+// This header holds the templates; pdt_band_{f64,f32,mixed,batch}.hip instantiate them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+#include <type_traits>
+
+#include "pdt_device.h"
+#include "pdt_internal.h"
+#include "pdt_pmf.h"
+
+namespace pdt {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Acc;
+template <>
+struct Acc<double> {
+  typedef f64x4 type;
+  __device__ static __forceinline__ f64x4 mfma(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // tile row held in result register r of a lane in group kq = lane / 16
+  __device__ static __forceinline__ int row(int kq, int r) { return kq + 4 * r; }
+};
+template <>
+struct Acc<float> {
+  typedef f32x4 type;
+  __device__ static __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ int row(int kq, int r) { return 4 * kq + r; }
+};
+
+// ---------------------------------------------------------------------------------------
+// Forward band product O = F X, residuals and objective partials.
+//
+// One workgroup of KS waves per 16-probe tile; the waves split the tile's photon-number
+// range in 64-wide chunks (wave w takes chunks w, w + KS, ...), each prefetching the X
+// rows of the next PF contraction steps into a register ring.  Partial tiles are summed
+// in LDS in a fixed order, then each wave finishes 4 of the 16 probe rows.  Every
+// workgroup also sums the regulariser over a slice of rows.
+// ---------------------------------------------------------------------------------------
+constexpr int PF = 4;   // prefetch depth in contraction steps
+// KS (a template parameter, 4 or 8) waves per workgroup split the contraction; the
+// first four waves finish the tile's 16 rows in the epilogues.
+
+// sum the KS partial 16 x (16 NT) tiles of a workgroup into S (LDS, row stride ld)
+template <typename T, int NT, int KS, typename AccT>
+__device__ __forceinline__ void reduce_tiles(const AccT (&acc)[NT], double* S, int ld, int wv, int i, int kq) {
+  for (int w = 0; w < KS; ++w) {
+    if (wv == w) {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          double* p = S + Acc<T>::row(kq, r) * ld + nt * 16 + i;
+          *p = (w == 0) ? (double)acc[nt][r] : *p + (double)acc[nt][r];
+        }
+    }
+    __syncthreads();
+  }
+}
+
+// TS: storage type of X, O, R, P.  TC: MFMA operand type (TS, or float under TS = double
+// for the mixed path, whose forward product works on X_new - X_cur: FX_DELTA).
+template <typename TS, typename TC, int NT, int KS>
+__device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode, int tile,
+                                        int ntiles) {
+  if ((mode == FX_ITER || mode == FX_DELTA || mode == FX_EVAL_PREV || mode == FX_RESYNC) && st->done) return;
+  typedef TS T;
+  typedef typename Acc<TC>::type AccT;
+  const bool iter = mode == FX_ITER || mode == FX_DELTA;
+  constexpr int LDT = 16 * NT + 1;
+  __shared__ double S[16 * LDT];
+  __shared__ double red[KS];
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6;
+  const int lane = tid & 63;
+  const int i = lane & 15;
+  const int kq = lane >> 4;
+  const int M = pv.M, D = pv.D, N = pv.N, Npad = pv.Npad;
+
+  const int ix_cur = st->ix_cur;
+  const int ix_x = iter ? st->ix_new : (mode == FX_EVAL_PREV ? st->ix_prev : ix_cur);
+  const T* __restrict__ X = b.X[ix_x];
+  T* __restrict__ O = b.O[ix_x];
+  const T* __restrict__ Ocur = b.O[ix_cur];
+  // the mixed instantiation (float products on double storage) always forms the delta
+  constexpr bool delta = !std::is_same<TS, TC>::value;
+
+  const int d0 = tile << 4;
+  const int d = d0 + i;
+  const bool dval = d < D;
+  const double mu = dval ? pv.mu[d] : 0.0;
+  const int blo = dval ? pv.lo[d] : 1;
+  const int bhi = dval ? pv.hi[d] : 0;
+  const double tl = (dval && pv.lump) ? pv.tail[d] : 0.0;
+  const int lumpm = pv.lump ? M - 1 : -1;
+  const int mlo = pv.dt_mlo[tile];
+  const int mhi = pv.dt_mhi[tile];
+
+  AccT acc[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) acc[nt] = AccT{0, 0, 0, 0};
+
+  // Contraction step s of a 64-photon-number chunk at mb gives k-slot kq the photon
+  // number mb + 4 s + kq, so each lane walks its probe's row of F with stride 4 across
+  // the wave's whole (contiguous) share of the tile: F[d][m + 4] = F[d][m] mu^4 r4[m],
+  // r4[m] = 1 / ((m+1)(m+2)(m+3)(m+4)).  A lane takes a fresh anchor where its band
+  // starts and every 16 chunks.  X rows beyond M-1 are clamped: F is zero there.
+  auto load_step = [&](int mrow, TC (&dst)[NT], double& r) {
+    const int m = mrow < M - 1 ? mrow : M - 1;
+    const unsigned base = (unsigned)m * (unsigned)Npad + (unsigned)i;
+    if constexpr (delta) {
+      // the candidate step, written in FP32 by the transposed product's epilogue
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) dst[nt] = (TC)b.dX[base + 16u * nt];
+    } else {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) dst[nt] = (TC)X[base + 16u * nt];
+    }
+    r = pv.r4[mrow];
+  };
+  const int nch = mhi >= mlo ? (mhi - mlo) / kChunkM + 1 : 0;
+  const int c0 = (nch * wv) / KS;
+  const int c1 = (nch * (wv + 1)) / KS;
+  const double mu4 = (mu * mu) * (mu * mu);
+  TC xb[PF][NT];
+  double rb[PF];
+  if (c0 < c1) {
+#pragma unroll
+    for (int q = 0; q < PF; ++q) load_step(mlo + kChunkM * c0 + 4 * q + kq, xb[q], rb[q]);
+  }
+  double p = 0.0;
+  for (int c = c0; c < c1; ++c) {
+    const int mb = mlo + kChunkM * c;
+    const bool more = c + 1 < c1;
+    const int ma = mb + kq;
+    if ((p == 0.0 || ((c - c0) & 15) == 0) && ma <= bhi && ma + 60 >= blo) p = poisson_pmf(ma, mu);
+#pragma unroll
+    for (int st = 0; st < 16; ++st) {
+      const int m = ma + 4 * st;
+      double f = (m >= blo && m <= bhi) ? p : 0.0;
+      f = (m == lumpm && m >= blo && m <= bhi) ? tl : f;
+      p *= mu4 * rb[st % PF];
+      const TC a = (TC)f;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[nt] = Acc<TC>::mfma(a, xb[st % PF][nt], acc[nt]);
+      if (st + PF < 16) load_step(m + 4 * PF, xb[st % PF], rb[st % PF]);
+      else if (more) load_step(m + 4 * PF, xb[st % PF], rb[st % PF]);
+    }
+  }
+  reduce_tiles<TC, NT, KS>(acc, S, LDT, wv, i, kq);
+
+  // epilogue: wave wv finishes probe rows 4 wv + kq
+  T beta_acc = 0;
+  if (iter) {
+    const double t = st->t;
+    const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+    const double tnn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * tn * tn));
+    beta_acc = (T)((tn - 1.0) / tnn);
+  }
+  double part = 0.0;
+  const int dd = d0 + 4 * wv + kq;
+  if (wv < 4 && dd < D) {
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int n = nt * 16 + i;
+      const size_t off = (size_t)dd * Npad + n;
+      const T oc_ = iter ? Ocur[off] : (T)0;
+      const T o = delta ? oc_ + (T)S[(4 * wv + kq) * LDT + n] : (T)S[(4 * wv + kq) * LDT + n];
+      const T pv_ = b.P[off];
+      O[off] = o;
+      if (n < N) {
+        const double e = (double)o - (double)pv_;
+        part += e * e;
+      }
+      if (iter) {
+        const T oc = oc_;
+        b.R_acc[off] = o + beta_acc * (o - oc) - pv_;
+        b.R_rej[off] = oc - pv_;
+      } else if (mode == FX_RESYNC) {
+        // the next step's residual if it keeps its momentum (F Y = O + beta (O - O_prev))
+        // or restarts, both from exact products
+        const T op = b.O[st->ix_prev][off];
+        b.R_acc[off] = o + (T)st->beta * (o - op) - pv_;
+        b.R_rej[off] = o - pv_;
+      } else if (mode != FX_EVAL_PREV) {
+        b.R_rej[off] = o - pv_;
+      }
+    }
+  }
+
+  // regulariser over this workgroup's slice of row pairs
+  if (pv.gamma != 0.0 && M > 1) {
+    double reg = 0.0;
+    const long long pairs = (long long)(M - 1);
+    const long long W = ntiles;
+    const long long per = (pairs + W - 1) / W;
+    const long long r0 = (long long)tile * per;
+    const long long r1 = r0 + per < pairs ? r0 + per : pairs;
+    const long long cnt = (r1 > r0 ? r1 - r0 : 0) * (long long)N;
+    for (long long q = tid; q < cnt; q += 64 * KS) {
+      const long long m = r0 + q / N;
+      const int n = (int)(q % N);
+      const double e = (double)X[m * Npad + n] - (double)X[(m + 1) * Npad + n];
+      reg += e * e;
+    }
+    part += pv.gamma * reg;
+  }
+  part = group_sum<64>(part);
+  if (lane == 0) red[wv] = part;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < KS; ++w) s += red[w];
+    b.partials[tile] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Transposed band product, regulariser gradient and the projected step.
+//
+// One workgroup of KS waves per 16-row tile of Pi; the waves split the tile's probe
+// range in 64-probe chunks.  Per chunk a wave generates F[d][m0..m0+15] for its 64
+// probes (lane = probe, recursion along m) into its own LDS slice and reads it back
+// transposed as the MFMA A operand; the R rows of the next PF steps are prefetched.
+// ---------------------------------------------------------------------------------------
+template <typename TS, typename TC, int NT, int KS>
+__device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode,
+                                         double step, int mt) {
+  if (mode == FTR_STEP && st->done) return;
+  typedef TS T;
+  typedef typename Acc<TC>::type AccT;
+  constexpr int LDT = 16 * NT + 1;
+  // the F^T staging tiles of the main loop and the reduction tile share one LDS block
+  constexpr int kFt = KS * kChunkD * 17, kS = 16 * LDT;
+  __shared__ double lds[kFt > kS ? kFt : kS];
+  double(*Ft)[kChunkD][17] = reinterpret_cast<double(*)[kChunkD][17]>(lds);
+  double* S = lds;
+  __shared__ double red[KS];
+
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6;
+  const int lane = tid & 63;
+  const int i = lane & 15;
+  const int kq = lane >> 4;
+  const int m0 = mt << 4;
+  const int M = pv.M, N = pv.N, Npad = pv.Npad;
+  const int lumpm = pv.lump ? M - 1 : -1;
+  const int dlo = pv.mt_dlo[mt];
+  const int dhi = pv.mt_dhi[mt];
+  const T* __restrict__ R = (mode == FTR_STEP && st->sel_acc) ? b.R_acc : b.R_rej;
+
+  AccT acc[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) acc[nt] = AccT{0, 0, 0, 0};
+
+  // probes beyond dhi are clamped: their generated F entries are zero
+  auto load_r = [&](int drow, TC (&dst)[NT]) {
+    const int dd = drow < dhi ? drow : dhi;
+    const unsigned base = (unsigned)(dd > 0 ? dd : 0) * (unsigned)Npad + (unsigned)i;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) dst[nt] = (TC)R[base + 16u * nt];
+  };
+  const int nchunks = dhi >= dlo ? (dhi - dlo) / kChunkD + 1 : 0;
+  const int rounds = (nchunks + KS - 1) / KS;
+  constexpr int stride = kChunkD * KS;
+  // the tile's 16 photon numbers are shared by every probe: 1/(m+1) once per workgroup
+  double inv[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) inv[j] = pv.rinv[m0 + j + 1];
+
+  // generator state of one probe (lane) for a chunk: F[d][m0 + j], j = 0..15.  The
+  // probe parameters are loaded one round before the anchor is formed from them.
+  struct Gen {
+    double mu, tl, p;
+    int blo, bhi;
+  };
+  const double* __restrict__ anc = pv.anchors + pv.mt_aoff[mt];
+  auto gen_params = [&](int dcc) {
+    Gen g{0.0, 0.0, 0.0, 1, 0};
+    const int d = dcc + lane;
+    if (d <= dhi) {
+      g.mu = pv.mu[d];
+      g.blo = pv.lo[d];
+      g.bhi = pv.hi[d];
+      g.tl = pv.lump ? pv.tail[d] : 0.0;
+      g.p = anc[d - dlo];  // F[d][m0] from the setup table (0 where the band misses the tile)
+    }
+    return g;
+  };
+  auto gen_anchor = [&](Gen&) {};
+  auto gen_step = [&](Gen& g, int j) -> double {
+    const int m = m0 + j;
+    double f = (m >= g.blo && m <= g.bhi) ? g.p : 0.0;
+    f = (m == lumpm && m >= g.blo && m <= g.bhi) ? g.tl : f;
+    g.p *= g.mu * inv[j];
+    return f;
+  };
+
+  int dc = dlo + kChunkD * wv;
+  TC rb[PF][NT];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) load_r(dc + 16 * kq + p, rb[p]);
+  double vals[16];
+  Gen gn;  // parameters of the chunk after the one being generated
+  if (rounds > 0) {
+    Gen g = gen_params(dc);
+    gen_anchor(g);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) vals[j] = gen_step(g, j);
+    gn = gen_params(dc + stride);
+  }
+  for (int rd = 0; rd < rounds; ++rd, dc += stride) {
+    const int dcn = dc + stride;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) Ft[wv][lane][j] = vals[j];
+    __syncthreads();
+    // the next chunk's F values are generated between this chunk's MFMAs
+    Gen g = gn;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const TC a = (TC)Ft[wv][16 * kq + s][i];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[nt] = Acc<TC>::mfma(a, rb[s % PF][nt], acc[nt]);
+      if (s + PF < 16) load_r(dc + 16 * kq + s + PF, rb[s % PF]);
+      else load_r(dcn + 16 * kq + s + PF - 16, rb[s % PF]);
+      if (s == 1) gen_anchor(g);
+      if (s == 2) gn = gen_params(dcn + stride);
+      if (s >= 2) vals[s - 2] = gen_step(g, s - 2);
+    }
+    vals[14] = gen_step(g, 14);
+    vals[15] = gen_step(g, 15);
+    __syncthreads();
+  }
+  reduce_tiles<TC, NT, KS>(acc, S, LDT, wv, i, kq);
+
+  // epilogue: wave wv finishes rows m0 + 4 wv + kq (one row per 16-lane group)
+  const int m = m0 + 4 * wv + kq;
+  const bool mval = wv < 4 && m < M;
+  const T g2 = (T)(2.0 * pv.gamma);
+  if (mode == FTR_STEP) {
+    const T beta = (T)st->beta;
+    const T* __restrict__ Xc = b.X[st->ix_cur];
+    const T* __restrict__ Xp = b.X[st->ix_prev];
+    T* __restrict__ Xn = b.X[st->ix_new];
+    // row-scaled step: this group's row takes step * w_m
+    const T stp = (T)((b.wrow && mval) ? step * b.wrow[m] : step);
+    // the mixed instantiation also hands the forward product the step X_new - X_cur in FP32
+    constexpr bool delta = !std::is_same<TS, TC>::value;
+    T z[1][NT];
+    T xcs[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int n = nt * 16 + i;
+      T zz = (n < N) ? (T)0 : neg_huge<T>();
+      xcs[nt] = 0;
+      if (mval && n < N) {
+        const size_t off = (size_t)m * Npad + n;
+        const T xc = Xc[off];
+        xcs[nt] = xc;
+        const T y = xc + beta * (xc - Xp[off]);
+        T ly = 0;
+        if (m > 0) {
+          const T xm = Xc[off - Npad];
+          ly += y - (xm + beta * (xm - Xp[off - Npad]));
+        }
+        if (m < M - 1) {
+          const T xq = Xc[off + Npad];
+          ly += y - (xq + beta * (xq - Xp[off + Npad]));
+        }
+        const T g = (T)2 * (T)S[(4 * wv + kq) * LDT + n] + g2 * ly;
+        zz = y - stp * g;
+      }
+      z[0][nt] = zz;
+    }
+    T tau[1];
+    simplex_threshold<T, 16, NT, 1, 8>(z, tau);
+    if (mval) {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int n = nt * 16 + i;
+        const T xn = (n < N) ? fmax(z[0][nt] - tau[0], (T)0) : (T)0;
+        Xn[(size_t)m * Npad + n] = xn;
+        if constexpr (delta) b.dX[(size_t)m * Npad + n] = (float)(xn - xcs[nt]);
+      }
+    }
+  } else {
+    // gradient at X_cur (R_rej = F X_cur - P) and the KKT residual partial
+    const T* __restrict__ Xc = b.X[st->ix_cur];
+    double part = 0.0;
+    T g[NT], x[NT];
+    T gmin = FLT_MAX;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int n = nt * 16 + i;
+      g[nt] = 0;
+      x[nt] = 0;
+      if (mval && n < N) {
+        const size_t off = (size_t)m * Npad + n;
+        const T xc = Xc[off];
+        T lx = 0;
+        if (m > 0) lx += xc - Xc[off - Npad];
+        if (m < M - 1) lx += xc - Xc[off + Npad];
+        g[nt] = (T)2 * (T)S[(4 * wv + kq) * LDT + n] + g2 * lx;
+        x[nt] = xc;
+        gmin = fmin(gmin, g[nt]);
+      }
+      if (mval) b.G[(size_t)m * Npad + n] = g[nt];
+    }
+    gmin = group_min<16>(gmin);
+    if (mval) {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int n = nt * 16 + i;
+        if (n < N) {
+          const double e = (double)x[nt] * ((double)g[nt] - (double)gmin);
+          part += e * e;
+        }
+      }
+    }
+    part = group_sum<64>(part);
+    if (lane == 0) red[wv] = part;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < KS; ++w) s += red[w];
+      b.partials[mt] = s;
+    }
+  }
+}
+
+
+template <typename TS, typename TC, int NT, int KS>
+__global__ __launch_bounds__(64 * KS) void fx_kernel(ProbView pv, Bufs<TS> b, SolverState* st, int mode) {
+  fx_body<TS, TC, NT, KS>(pv, b, st, mode, blockIdx.x, gridDim.x);
+}
+
+template <typename TS, typename TC, int NT, int KS>
+__global__ __launch_bounds__(64 * KS) void ftr_kernel(ProbView pv, Bufs<TS> b, SolverState* st, int mode,
+                                                       double step) {
+  ftr_body<TS, TC, NT, KS>(pv, b, st, mode, step, blockIdx.x);
+}
+
+// Batched launches: one workgroup per (instance, tile) item of a work list; every
+// instance carries its own problem view, buffers, state and step.
+template <typename TS, typename TC, int NT, int KS>
+__global__ __launch_bounds__(64 * KS) void fx_batch_kernel(const BatchInst<TS>* insts, const int2* items, int mode) {
+  const int2 it = items[blockIdx.x];
+  const BatchInst<TS>& I = insts[it.x];
+  fx_body<TS, TC, NT, KS>(I.pv, I.b, I.st, mode, it.y, I.n_dt);
+}
+
+template <typename TS, typename TC, int NT, int KS>
+__global__ __launch_bounds__(64 * KS) void ftr_batch_kernel(const BatchInst<TS>* insts, const int2* items,
+                                                             int mode) {
+  const int2 it = items[blockIdx.x];
+  const BatchInst<TS>& I = insts[it.x];
+  ftr_body<TS, TC, NT, KS>(I.pv, I.b, I.st, mode, I.step, it.y);
+}
+
+
+// ---------------------------------------------------------------------------------------
+// Launchers: the column-tile class NT = Npad / 16 and the waves per workgroup KS (4 or 8,
+// from the problem view, or per work list for batches) select the instantiation.
+// ---------------------------------------------------------------------------------------
+template <typename TS, typename TC, int NT, int KS>
+static void fx_go(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode, hipStream_t s) {
+  hipLaunchKernelGGL((fx_kernel<TS, TC, NT, KS>), dim3(fx_num_waves(pv)), dim3(64 * KS), 0, s, pv, b, st, mode);
+}
+template <typename TS, typename TC, int NT, int KS>
+static void ftr_go(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode, double step,
+                   hipStream_t s) {
+  hipLaunchKernelGGL((ftr_kernel<TS, TC, NT, KS>), dim3(ftr_num_waves(pv)), dim3(64 * KS), 0, s, pv, b, st, mode,
+                     step);
+}
+
+#define PDT_NT_SWITCH(NTV, CALL)                 \
+  switch (NTV) {                                 \
+    case 1: CALL(1); break;                      \
+    case 2: CALL(2); break;                      \
+    case 3: CALL(3); break;                      \
+    case 4: CALL(4); break;                      \
+    case 5: CALL(5); break;                      \
+    case 6: CALL(6); break;                      \
+    case 7: CALL(7); break;                      \
+    case 8: CALL(8); break;                      \
+    case 9: CALL(9); break;                      \
+    case 10: CALL(10); break;                    \
+    case 11: CALL(11); break;                    \
+    case 12: CALL(12); break;                    \
+    default: return hipErrorInvalidValue;        \
+  }
+
+template <typename TS, typename TC>
+hipError_t launch_fx(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode, hipStream_t s) {
+  if (pv.ks_fx == 8) {
+#define PDT_FX(K) fx_go<TS, TC, K, 8>(pv, b, st, mode, s)
+    PDT_NT_SWITCH(pv.Npad / 16, PDT_FX)
+#undef PDT_FX
+  } else if (pv.ks_fx == 4) {
+#define PDT_FX(K) fx_go<TS, TC, K, 4>(pv, b, st, mode, s)
+    PDT_NT_SWITCH(pv.Npad / 16, PDT_FX)
+#undef PDT_FX
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename TS, typename TC>
+hipError_t launch_ftr(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode, double step,
+                      hipStream_t s) {
+  if (pv.ks_ftr == 8) {
+#define PDT_FTR(K) ftr_go<TS, TC, K, 8>(pv, b, st, mode, step, s)
+    PDT_NT_SWITCH(pv.Npad / 16, PDT_FTR)
+#undef PDT_FTR
+  } else if (pv.ks_ftr == 4) {
+#define PDT_FTR(K) ftr_go<TS, TC, K, 4>(pv, b, st, mode, step, s)
+    PDT_NT_SWITCH(pv.Npad / 16, PDT_FTR)
+#undef PDT_FTR
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename TS, typename TC, int NT, int KS>
+static void fxb_go(const BatchInst<TS>* insts, const int2* items, int n_items, int mode, hipStream_t s) {
+  hipLaunchKernelGGL((fx_batch_kernel<TS, TC, NT, KS>), dim3(n_items), dim3(64 * KS), 0, s, insts, items, mode);
+}
+template <typename TS, typename TC, int NT, int KS>
+static void ftrb_go(const BatchInst<TS>* insts, const int2* items, int n_items, int mode, hipStream_t s) {
+  hipLaunchKernelGGL((ftr_batch_kernel<TS, TC, NT, KS>), dim3(n_items), dim3(64 * KS), 0, s, insts, items, mode);
+}
+
+template <typename TS, typename TC>
+hipError_t launch_fx_batch(int nt, int ks, const BatchInst<TS>* insts, const int2* items, int n_items, int mode,
+                           hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (ks == 8) {
+#define PDT_FXB(K) fxb_go<TS, TC, K, 8>(insts, items, n_items, mode, s)
+    PDT_NT_SWITCH(nt, PDT_FXB)
+#undef PDT_FXB
+  } else if (ks == 4) {
+#define PDT_FXB(K) fxb_go<TS, TC, K, 4>(insts, items, n_items, mode, s)
+    PDT_NT_SWITCH(nt, PDT_FXB)
+#undef PDT_FXB
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename TS, typename TC>
+hipError_t launch_ftr_batch(int nt, int ks, const BatchInst<TS>* insts, const int2* items, int n_items, int mode,
+                            hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (ks == 8) {
+#define PDT_FTRB(K) ftrb_go<TS, TC, K, 8>(insts, items, n_items, mode, s)
+    PDT_NT_SWITCH(nt, PDT_FTRB)
+#undef PDT_FTRB
+  } else if (ks == 4) {
+#define PDT_FTRB(K) ftrb_go<TS, TC, K, 4>(insts, items, n_items, mode, s)
+    PDT_NT_SWITCH(nt, PDT_FTRB)
+#undef PDT_FTRB
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pdt

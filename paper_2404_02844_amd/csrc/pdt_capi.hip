@@ -14,6 +14,7 @@
 
 #include "pdt.h"
 #include "pdt_internal.h"
+#include "pdt_tuning.h"
 #include "pdt_mlp.h"
 
 using namespace pdt;
@@ -60,6 +61,9 @@ struct Arena {
     ptrs.clear();
   }
 };
+
+// kernel variants of the iteration: storage / MFMA type
+enum Variant { VAR_FP64 = 0, VAR_FP32 = 1, VAR_MIXED = 2 };
 
 template <typename T>
 struct Work {
@@ -113,20 +117,27 @@ struct Instance {
   double graph_step[3] = {0.0, 0.0, 0.0};
   double* graph_hist[3] = {nullptr, nullptr, nullptr};
   const double* graph_w[3] = {nullptr, nullptr, nullptr};
+  // waves per workgroup forced per variant and kernel (0: from the tuning table)
+  int ks_force[3][2] = {{0, 0}, {0, 0}, {0, 0}};
 };
 
 }  // namespace
 
 struct pdt_model_s;
 
+// One launch of a batched phase: the items of one column-tile class and workgroup shape.
+struct LaunchList {
+  int nt = 0, ks = 4;
+  int2* items = nullptr;
+  int n = 0;
+};
+
 struct BatchPlan {
   int prec = -1;
   int scaling = -1;
   std::vector<double> steps;
   void* insts = nullptr;          // device BatchInst<T>[n]
-  std::vector<int> nt_class;      // column-tile class of each launch group
-  std::vector<int2*> fx_items, ftr_items;
-  std::vector<int> n_fx, n_ftr;
+  std::vector<LaunchList> fx, ftr;
   hipGraphExec_t graph = nullptr;
 };
 
@@ -184,6 +195,20 @@ ProbView view_of(const Instance& I) {
   pv.Npad = (int)I.Npad;
   pv.lump = I.lump;
   pv.gamma = I.gamma;
+  return pv;
+}
+
+// Waves per workgroup of the band kernels for the view's column-tile class and tile
+// counts: forced per instance, or from the tuning table.
+void apply_ks(ProbView& pv, const Instance& I, int var) {
+  const int nt = pv.Npad / 16;
+  pv.ks_fx = I.ks_force[var][0] ? I.ks_force[var][0] : choose_ks(var, 0, nt, (pv.D + 15) / 16);
+  pv.ks_ftr = I.ks_force[var][1] ? I.ks_force[var][1] : choose_ks(var, 1, nt, (pv.M + 15) / 16);
+}
+
+ProbView view_var(const Instance& I, int var) {
+  ProbView pv = view_of(I);
+  apply_ks(pv, I, var);
   return pv;
 }
 
@@ -255,6 +280,7 @@ double lipschitz_power(pdt_problem_s* pb, Instance& I, int iters, const double* 
   ProbView pv = view_of(I);
   pv.N = 1;
   pv.Npad = 16;
+  apply_ks(pv, I, VAR_FP64);
   const size_t xm = (size_t)I.M * 16, od = (size_t)I.D * 16;
   try {
     Work<double> w;
@@ -438,7 +464,7 @@ SolverState read_state(hipStream_t s, const SolverState* src) {
 // f and (optionally) the gradient of the FP64 iterate already in I.w64.X[0].
 double eval_fp64(pdt_problem_s* pb, Instance& I, bool grad, double* kkt_out) {
   hipStream_t s = pb->stream;
-  const ProbView pv = view_of(I);
+  const ProbView pv = view_var(I, VAR_FP64);
   Bufs<double> b = bufs_of(I, I.w64, nullptr);
   init_state(s, I.st_eval, 0, 0.0, 0.0);
   HIPCHK(launch_fx<double>(pv, b, I.st_eval, FX_EVAL, s));
@@ -459,8 +485,6 @@ double eval_fp64(pdt_problem_s* pb, Instance& I, bool grad, double* kkt_out) {
 
 constexpr int64_t kGraphIters = 64;
 
-// kernel variants of the iteration: storage / MFMA type
-enum Variant { VAR_FP64 = 0, VAR_FP32 = 1, VAR_MIXED = 2 };
 
 template <typename TS, typename TC>
 void enqueue_iters(const ProbView& pv, const Bufs<TS>& b, SolverState* st, double step, int64_t n, bool delta,
@@ -473,6 +497,15 @@ void enqueue_iters(const ProbView& pv, const Bufs<TS>& b, SolverState* st, doubl
   }
 }
 
+// End of a chunk of the mixed path: exact products of X_prev and X_cur replace the
+// FP32-updated ones, with both residual candidates and f_cur formed from them.
+template <typename TS>
+void enqueue_resync(const ProbView& pv64, const Bufs<TS>& b, SolverState* st, hipStream_t s) {
+  HIPCHK((launch_fx<TS, TS>(pv64, b, st, FX_EVAL_PREV, s)));
+  HIPCHK((launch_fx<TS, TS>(pv64, b, st, FX_RESYNC, s)));
+  HIPCHK(launch_decide(b.partials, fx_num_waves(pv64), st, nullptr, DEC_RESYNC, s));
+}
+
 void drop_graphs(Instance& I) {
   for (int v = 0; v < 3; ++v) {
     if (I.graph[v]) (void)hipGraphExecDestroy(I.graph[v]);
@@ -481,8 +514,9 @@ void drop_graphs(Instance& I) {
 }
 
 // One graph = kGraphIters iterations of a variant.  The mixed variant forms F X_new by
-// the FP32 delta F (X_new - X_cur) on FP64 storage, so it ends with an exact FP64
-// forward product of the current iterate that removes the drift of those updates.
+// the FP32 delta F (X_new - X_cur) on FP64 storage, so it ends with exact FP64 forward
+// products of the previous and current iterates and the exact objective, which remove
+// the drift of those updates.
 template <typename TS, typename TC>
 hipGraphExec_t get_graph(pdt_problem_s* pb, Instance& I, int var, const Bufs<TS>& b, double step) {
   if (I.graph[var] && I.graph_step[var] == step && I.graph_hist[var] == b.history && I.graph_w[var] == b.wrow)
@@ -493,12 +527,13 @@ hipGraphExec_t get_graph(pdt_problem_s* pb, Instance& I, int var, const Bufs<TS>
   // stream, which cannot be captured); replayed on the caller's stream
   if (!pb->capture) HIPCHK(hipStreamCreateWithFlags(&pb->capture, hipStreamNonBlocking));
   hipStream_t cs = pb->capture;
-  const ProbView pv = view_of(I);
+  const ProbView pv = view_var(I, var);
+  const ProbView pv64 = view_var(I, VAR_FP64);
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   try {
     enqueue_iters<TS, TC>(pv, b, I.st, step, kGraphIters, var == VAR_MIXED, cs);
-    if (var == VAR_MIXED) HIPCHK((launch_fx<TS, TS>(pv, b, I.st, FX_EVAL, cs)));
+    if (var == VAR_MIXED) enqueue_resync<TS>(pv64, b, I.st, cs);
   } catch (...) {
     (void)hipStreamEndCapture(cs, &g);
     if (g) (void)hipGraphDestroy(g);
@@ -523,7 +558,8 @@ template <typename TS, typename TC>
 SolverState run_chunks(pdt_problem_s* pb, Instance& I, int var, const Bufs<TS>& b, double step, int64_t budget,
                        bool stagnate) {
   hipStream_t s = pb->stream;
-  const ProbView pv = view_of(I);
+  const ProbView pv = view_var(I, var);
+  const ProbView pv64 = view_var(I, VAR_FP64);
   SolverState h = read_state(s, I.st);
   int64_t launched = 0;
   while (launched < budget && !h.done) {
@@ -534,7 +570,7 @@ SolverState run_chunks(pdt_problem_s* pb, Instance& I, int var, const Bufs<TS>& 
     } else {
       const int64_t n = budget - launched;
       enqueue_iters<TS, TC>(pv, b, I.st, step, n, var == VAR_MIXED, s);
-      if (var == VAR_MIXED) HIPCHK((launch_fx<TS, TS>(pv, b, I.st, FX_EVAL, s)));
+      if (var == VAR_MIXED) enqueue_resync<TS>(pv64, b, I.st, s);
       launched += n;
     }
     h = read_state(s, I.st);
@@ -547,7 +583,7 @@ template <typename T>
 void run_loop(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double step, const double* wrow, int var,
               SolverState& out) {
   hipStream_t s = pb->stream;
-  const ProbView pv = view_of(I);
+  const ProbView pv = view_var(I, var);
   Work<T>& w = work_of<T>(I);
   Bufs<T> b = bufs_of(I, w, o.history, wrow);
   HIPCHK(launch_fx<T>(pv, b, I.st, FX_INIT, s));
@@ -560,7 +596,7 @@ void run_loop(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double st
 void run_mixed(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double step, const double* wrow,
                SolverState& out, int64_t& refine_iters) {
   hipStream_t s = pb->stream;
-  const ProbView pv = view_of(I);
+  const ProbView pv = view_var(I, VAR_FP64);
   if (!I.w64.dX) {
     const size_t xm = (size_t)I.M * I.Npad;
     I.w64.dX = pb->arena.alloc<float>(xm);
@@ -582,7 +618,8 @@ namespace {
 template <typename T, typename TC = T>
 void replay_impl(pdt_problem_s* pb, Instance& I, int kernel, int64_t reps) {
   hipStream_t s = pb->stream;
-  const ProbView pv = view_of(I);
+  const int var = std::is_same<T, float>::value ? VAR_FP32 : (std::is_same<T, TC>::value ? VAR_FP64 : VAR_MIXED);
+  const ProbView pv = view_var(I, var);
   Bufs<T> b = bufs_of(I, work_of<T>(I), nullptr);
   SolverState s0;
   std::memset(&s0, 0, sizeof(s0));
@@ -662,6 +699,39 @@ pdt_status pdt_problem_bands(pdt_problem_t pb, int32_t* lo, int32_t* hi, double*
   if (tail) std::memcpy(tail, I.tail_h.data(), I.tail_h.size() * sizeof(double));
   if (lipschitz) *lipschitz = I.L_hat;
   if (nnz) *nnz = I.nnz;
+  return PDT_OK;
+}
+
+pdt_status pdt_problem_set_tiles(pdt_problem_t pb, int64_t instance, int precision, int ks_fx, int ks_ftr) {
+  if (!pb) return set_err(PDT_ERR_INVALID_ARG, "problem is NULL");
+  if (instance < 0 || instance >= (int64_t)pb->inst.size()) return set_err(PDT_ERR_INVALID_ARG, "bad instance");
+  if (precision != PDT_FP64 && precision != PDT_FP32 && precision != PDT_MIXED)
+    return set_err(PDT_ERR_INVALID_ARG, "precision not supported");
+  auto ok = [](int k) { return k == 0 || k == 4 || k == 8; };
+  if (!ok(ks_fx) || !ok(ks_ftr)) return set_err(PDT_ERR_INVALID_ARG, "waves per workgroup must be 0, 4 or 8");
+  try {
+    (void)hipStreamSynchronize(pb->stream);
+    Instance& I = pb->inst[(size_t)instance];
+    I.ks_force[precision][0] = ks_fx;
+    I.ks_force[precision][1] = ks_ftr;
+    drop_graphs(I);
+    if (pb->plan.graph) (void)hipGraphExecDestroy(pb->plan.graph);
+    pb->plan.graph = nullptr;
+    pb->plan.prec = -1;
+    return PDT_OK;
+  } catch (...) {
+    return status_of_current_exception();
+  }
+}
+
+pdt_status pdt_problem_tiles(pdt_problem_t pb, int64_t instance, int precision, int* ks_fx, int* ks_ftr) {
+  if (!pb) return set_err(PDT_ERR_INVALID_ARG, "problem is NULL");
+  if (instance < 0 || instance >= (int64_t)pb->inst.size()) return set_err(PDT_ERR_INVALID_ARG, "bad instance");
+  if (precision != PDT_FP64 && precision != PDT_FP32 && precision != PDT_MIXED)
+    return set_err(PDT_ERR_INVALID_ARG, "precision not supported");
+  const ProbView pv = view_var(pb->inst[(size_t)instance], precision);
+  if (ks_fx) *ks_fx = pv.ks_fx;
+  if (ks_ftr) *ks_ftr = pv.ks_ftr;
   return PDT_OK;
 }
 
@@ -1139,13 +1209,17 @@ void build_plan(pdt_problem_s* pb, int prec, int scaling, const std::vector<doub
   pb->plan_arena.release();
   hipStream_t s = pb->stream;
   const size_t n = pb->inst.size();
+  const int var = prec == PDT_FP32 ? VAR_FP32 : VAR_FP64;
   std::vector<BatchInst<T>> host(n);
-  // per column-tile class: items with their band work as the cost
-  std::vector<std::vector<std::pair<int64_t, int2>>> fx(kMaxNT + 1), ftr(kMaxNT + 1);
+  // per (column-tile class, workgroup shape): items with their band work as the cost.
+  // Each instance keeps the workgroup shape its single solve would use, so the batch
+  // reproduces the single solves bit for bit.
+  auto key = [](int nt, int ks) { return 2 * nt + (ks == 8 ? 1 : 0); };
+  std::vector<std::vector<std::pair<int64_t, int2>>> fx(2 * kMaxNT + 2), ftr(2 * kMaxNT + 2);
   for (size_t k = 0; k < n; ++k) {
     Instance& I = pb->inst[k];
     BatchInst<T> bi;
-    bi.pv = view_of(I);
+    bi.pv = view_var(I, var);
     bi.b = bufs_of(I, work_of<T>(I), nullptr, scaling == PDT_STEP_DIAG ? I.wrow : nullptr);
     bi.st = I.st;
     bi.step = steps[k];
@@ -1153,6 +1227,7 @@ void build_plan(pdt_problem_s* pb, int prec, int scaling, const std::vector<doub
     bi.n_mt = ftr_num_waves(bi.pv);
     host[k] = bi;
     const int nt = (int)(I.Npad / 16);
+    const int kfx = key(nt, bi.pv.ks_fx), kftr = key(nt, bi.pv.ks_ftr);
     for (int t = 0; t < bi.n_dt; ++t) {
       int64_t lo = INT64_MAX, hi = -1;
       for (int d = 16 * t; d < std::min<int64_t>(16 * t + 16, I.D); ++d) {
@@ -1160,30 +1235,31 @@ void build_plan(pdt_problem_s* pb, int prec, int scaling, const std::vector<doub
         lo = std::min<int64_t>(lo, I.lo_h[d]);
         hi = std::max<int64_t>(hi, I.hi_h[d]);
       }
-      fx[nt].push_back({(hi >= lo ? hi - lo + 1 : 0) * nt, int2{(int)k, t}});
+      fx[kfx].push_back({(hi >= lo ? hi - lo + 1 : 0) * nt, int2{(int)k, t}});
     }
-    for (int t = 0; t < bi.n_mt; ++t) ftr[nt].push_back({(int64_t)nt, int2{(int)k, t}});
+    for (int t = 0; t < bi.n_mt; ++t) ftr[kftr].push_back({(int64_t)nt, int2{(int)k, t}});
   }
   P.insts = pb->plan_arena.alloc<BatchInst<T>>(n);
   HIPCHK(hipMemcpyAsync(P.insts, host.data(), n * sizeof(BatchInst<T>), hipMemcpyHostToDevice, s));
-  for (int nt = 1; nt <= kMaxNT; ++nt) {
-    if (fx[nt].empty() && ftr[nt].empty()) continue;
-    auto by_cost = [](const std::pair<int64_t, int2>& a, const std::pair<int64_t, int2>& b) {
-      return a.first > b.first;
-    };
-    std::stable_sort(fx[nt].begin(), fx[nt].end(), by_cost);
-    std::vector<int2> a, c;
-    for (auto& e : fx[nt]) a.push_back(e.second);
-    for (auto& e : ftr[nt]) c.push_back(e.second);
-    int2* da = pb->plan_arena.alloc<int2>(a.size());
-    int2* dc = pb->plan_arena.alloc<int2>(c.size());
-    HIPCHK(hipMemcpyAsync(da, a.data(), a.size() * sizeof(int2), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(dc, c.data(), c.size() * sizeof(int2), hipMemcpyHostToDevice, s));
-    P.nt_class.push_back(nt);
-    P.fx_items.push_back(da);
-    P.ftr_items.push_back(dc);
-    P.n_fx.push_back((int)a.size());
-    P.n_ftr.push_back((int)c.size());
+  auto by_cost = [](const std::pair<int64_t, int2>& a, const std::pair<int64_t, int2>& b) {
+    return a.first > b.first;
+  };
+  auto upload = [&](std::vector<std::pair<int64_t, int2>>& v, int c, std::vector<LaunchList>& out) {
+    if (v.empty()) return;
+    std::stable_sort(v.begin(), v.end(), by_cost);
+    std::vector<int2> items;
+    for (auto& e : v) items.push_back(e.second);
+    LaunchList L;
+    L.nt = c / 2;
+    L.ks = (c & 1) ? 8 : 4;
+    L.n = (int)items.size();
+    L.items = pb->plan_arena.alloc<int2>(items.size());
+    HIPCHK(hipMemcpyAsync(L.items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    out.push_back(L);
+  };
+  for (int c = 0; c < 2 * kMaxNT + 2; ++c) {
+    upload(fx[c], c, P.fx);
+    upload(ftr[c], c, P.ftr);
   }
   HIPCHK(hipStreamSynchronize(s));
   P.prec = prec;
@@ -1197,10 +1273,9 @@ void enqueue_batch_iters(pdt_problem_s* pb, int64_t iters, hipStream_t s) {
   const BatchInst<T>* insts = static_cast<const BatchInst<T>*>(P.insts);
   const int n = (int)pb->inst.size();
   for (int64_t k = 0; k < iters; ++k) {
-    for (size_t c = 0; c < P.nt_class.size(); ++c)
-      HIPCHK((launch_ftr_batch<T, T>(P.nt_class[c], insts, P.ftr_items[c], P.n_ftr[c], FTR_STEP, s)));
-    for (size_t c = 0; c < P.nt_class.size(); ++c)
-      HIPCHK((launch_fx_batch<T, T>(P.nt_class[c], insts, P.fx_items[c], P.n_fx[c], FX_ITER, s)));
+    for (const LaunchList& L : P.ftr)
+      HIPCHK((launch_ftr_batch<T, T>(L.nt, L.ks, insts, L.items, L.n, FTR_STEP, s)));
+    for (const LaunchList& L : P.fx) HIPCHK((launch_fx_batch<T, T>(L.nt, L.ks, insts, L.items, L.n, FX_ITER, s)));
     HIPCHK(launch_decide_batch<T>(insts, n, DEC_ITER, s));
   }
 }
@@ -1211,8 +1286,7 @@ void run_batch(pdt_problem_s* pb, const pdt_solve_opts& o, int prec, std::vector
   BatchPlan& P = pb->plan;
   const BatchInst<T>* insts = static_cast<const BatchInst<T>*>(P.insts);
   const int n = (int)pb->inst.size();
-  for (size_t c = 0; c < P.nt_class.size(); ++c)
-    HIPCHK((launch_fx_batch<T, T>(P.nt_class[c], insts, P.fx_items[c], P.n_fx[c], FX_INIT, s)));
+  for (const LaunchList& L : P.fx) HIPCHK((launch_fx_batch<T, T>(L.nt, L.ks, insts, L.items, L.n, FX_INIT, s)));
   HIPCHK(launch_decide_batch<T>(insts, n, DEC_INIT, s));
   if (o.max_iters >= kGraphIters && !P.graph) {
     if (!pb->capture) HIPCHK(hipStreamCreateWithFlags(&pb->capture, hipStreamNonBlocking));

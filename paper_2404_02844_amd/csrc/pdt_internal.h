@@ -29,9 +29,11 @@ constexpr int kChunkD = 64;       // probes per transposed-product chunk
 constexpr int kMaxNT = 12;        // outcome columns up to 192
 constexpr int kWave = 64;
 
-enum FxMode { FX_ITER = 0, FX_INIT = 1, FX_EVAL = 2, FX_DELTA = 3 };
+// FX_EVAL_PREV / FX_RESYNC: exact FP64 products of X_prev and X_cur that end each chunk
+// of the mixed path (O, both residual candidates and f of X_cur made exact again)
+enum FxMode { FX_ITER = 0, FX_INIT = 1, FX_EVAL = 2, FX_DELTA = 3, FX_EVAL_PREV = 4, FX_RESYNC = 5 };
 enum FtrMode { FTR_STEP = 0, FTR_GRAD = 1 };
-enum DecideMode { DEC_ITER = 0, DEC_INIT = 1, DEC_EVAL = 2 };
+enum DecideMode { DEC_ITER = 0, DEC_INIT = 1, DEC_EVAL = 2, DEC_RESYNC = 3 };
 
 // Device-resident solver state of one instance.  Written only by the decide kernel
 // (one thread, vector stores), read by every other kernel.
@@ -68,6 +70,8 @@ struct ProbView {
   const int* mt_dhi;
   int M, D, N, Npad, lump;
   double gamma;
+  int ks_fx = 4;   // waves per workgroup of the forward product (4 or 8)
+  int ks_ftr = 4;  // waves per workgroup of the transposed product (4 or 8)
 };
 
 template <typename T>
@@ -129,10 +133,10 @@ hipError_t launch_fill_rows(T* X, long long rows, int cols, int ld, T value, hip
 
 // batched launches over work lists of (instance, tile) items of one column-tile class nt
 template <typename TS, typename TC = TS>
-hipError_t launch_fx_batch(int nt, const BatchInst<TS>* insts, const int2* items, int n_items, int mode,
+hipError_t launch_fx_batch(int nt, int ks, const BatchInst<TS>* insts, const int2* items, int n_items, int mode,
                            hipStream_t s);
 template <typename TS, typename TC = TS>
-hipError_t launch_ftr_batch(int nt, const BatchInst<TS>* insts, const int2* items, int n_items, int mode,
+hipError_t launch_ftr_batch(int nt, int ks, const BatchInst<TS>* insts, const int2* items, int n_items, int mode,
                             hipStream_t s);
 template <typename TS>
 hipError_t launch_decide_batch(const BatchInst<TS>* insts, int n_inst, int mode, hipStream_t s);

@@ -62,6 +62,8 @@ def test_null_handles_are_rejected():
     f = ctypes.c_double()
     assert L.pdt_objective(None, None, ctypes.byref(f), None) == _pdt.PDT_ERR_INVALID_ARG
     assert L.pdt_project_simplex(None, None, 3, 3, None) == _pdt.PDT_ERR_INVALID_ARG
+    assert L.pdt_problem_set_tiles(None, 0, 0, 4, 4) == _pdt.PDT_ERR_INVALID_ARG
+    assert L.pdt_problem_tiles(None, 0, 0, None, None) == _pdt.PDT_ERR_INVALID_ARG
     L.pdt_destroy_problem(None)  # no-op
     assert "NULL" in _pdt.pdt_last_error()
 

@@ -39,18 +39,30 @@ def log(*a):
 PROFILE = os.path.join(ROOT, "profiles", "ftr_kernel_c2_m4096_n65_d5000.md")
 
 
+BAND_SOURCES = ("pdt_band.h", "pdt_device.h", "pdt_pmf.h", "pdt_internal.h", "pdt_tuning.h")
+
+
+def band_source_sha256() -> str:
+    """sha256 over the sources the band kernels are compiled from, in a fixed order."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in BAND_SOURCES:
+        with open(os.path.join(ROOT, "paper_2404_02844_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def measured_traffic():
     """HBM bytes per launch of the transposed product from the committed FETCH_SIZE /
     WRITE_SIZE summary, or None once the kernel source differs from the profiled one."""
-    import hashlib
     try:
         text = open(PROFILE).read()
-        src = open(os.path.join(ROOT, "paper_2404_02844_amd", "csrc", "pdt_kernels.hip"), "rb").read()
+        sha = band_source_sha256()
     except OSError:
         return None
     fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and line[:1].isalpha()
                   and line.split(": ", 1)[0] in ("kernel_source_sha256", "ftr_bytes_per_launch"))
-    if fields.get("kernel_source_sha256", "").strip() != hashlib.sha256(src).hexdigest():
+    if fields.get("kernel_source_sha256", "").strip() != sha:
         return None
     return float(fields["ftr_bytes_per_launch"])
 

@@ -295,6 +295,7 @@ double lipschitz_power(pdt_problem_s* pb, Instance& I, int iters, const double* 
     w.P = Pz;
     SolverState* st = tmp.alloc<SolverState>(1);
     double* lam = tmp.alloc<double>(1);
+    double* norm_scratch = tmp.alloc<double>(512);
     HIPCHK(hipMemsetAsync(Pz, 0, od * sizeof(double), s));
     std::vector<double> v0(xm, 0.0);
     const double inv = 1.0 / std::sqrt((double)I.M);
@@ -307,7 +308,7 @@ double lipschitz_power(pdt_problem_s* pb, Instance& I, int iters, const double* 
     for (int it = 0; it < iters; ++it) {
       HIPCHK(launch_fx<double>(pv, b, st, FX_EVAL, s));
       HIPCHK(launch_ftr<double>(pv, b, st, FTR_GRAD, 0.0, s));
-      HIPCHK(launch_power_normalize(w.G, w.X[0], (int)I.M, 16, wrow, lam, s));
+      HIPCHK(launch_power_normalize(w.G, w.X[0], (int)I.M, 16, wrow, norm_scratch, lam, s));
     }
     double lam_h = 0;
     HIPCHK(hipMemcpyAsync(&lam_h, lam, sizeof(double), hipMemcpyDeviceToHost, s));

@@ -1,0 +1,103 @@
+// Fixed-order reduction of the per-workgroup partials of f and the accept / reject
+// decision with the momentum scalars (Nesterov's t, beta) of the iteration.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "pdt_internal.h"
+
+namespace pdt {
+
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (tid < w) sh[tid] += sh[tid + w];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// The same sum over the values of the first 256 threads of a block of BS >= 256 threads
+// (the others only join the barriers), so every block size adds in one order.
+template <int BS>
+__device__ __forceinline__ double first256_sum(double v, double* sh) {
+  const int tid = threadIdx.x;
+  if (tid < 256) sh[tid] = v;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (tid < w) sh[tid] += sh[tid + w];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// Run by every thread of one block of BS threads (BS = 256, or the forward product's
+// workgroup when it takes the decision itself); the first 256 threads sum the partials.
+template <int BS>
+__device__ __forceinline__ void decide_body(const double* partials, int n, SolverState* st, double* history,
+                                            int mode) {
+  __shared__ double sh[256];
+  if ((mode == DEC_ITER || mode == DEC_RESYNC) && st->done) return;
+  double s = 0.0;
+  if (threadIdx.x < 256)
+    for (int k = threadIdx.x; k < n; k += 256) s += partials[k];
+  const double f = first256_sum<BS>(s, sh);
+  if (threadIdx.x != 0) return;
+  if (mode == DEC_EVAL) {
+    st->f_eval = f;
+    return;
+  }
+  if (mode == DEC_RESYNC) {
+    // the exact objective of the current iterate replaces the one accumulated from
+    // FP32 updates, so later acceptance tests compare against the true value
+    st->f_cur = f;
+    st->f_new = f;
+    return;
+  }
+  if (mode == DEC_INIT) {
+    st->f_cur = f;
+    st->f_new = f;
+    st->t = 1.0;
+    st->beta = 0.0;
+    st->ix_cur = 0;
+    st->ix_prev = 0;
+    st->ix_new = 1;
+    st->sel_acc = 0;
+    st->iter = 0;
+    st->rejects = 0;
+    st->done = (st->max_iters <= 0) ||
+               (st->f_star > 0.0 && f - st->f_star <= st->rel_tol * st->f_star) ? 1 : 0;
+    return;
+  }
+  const double t = st->t;
+  const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+  double tt;
+  st->f_new = f;
+  if (f <= st->f_cur) {
+    const int c = st->ix_cur, nw = st->ix_new;
+    st->ix_prev = c;
+    st->ix_cur = nw;
+    st->ix_new = 3 - c - nw;
+    st->f_cur = f;
+    st->sel_acc = 1;
+    tt = tn;
+  } else {
+    st->ix_prev = st->ix_cur;
+    st->sel_acc = 0;
+    st->rejects = st->rejects + 1;
+    tt = 1.0;
+  }
+  st->t = tt;
+  st->beta = (tt - 1.0) / (0.5 * (1.0 + sqrt(1.0 + 4.0 * tt * tt)));
+  const long long k = st->iter;
+  if (history) history[k] = st->f_cur;
+  st->iter = k + 1;
+  if (k + 1 >= st->max_iters) st->done = 1;
+  if (st->f_star > 0.0 && st->f_cur - st->f_star <= st->rel_tol * st->f_star) st->done = 1;
+}
+
+}  // namespace pdt

@@ -120,9 +120,10 @@ hipError_t launch_project_rows(const T* X, T* Y, long long rows, int cols, int l
                                hipStream_t s);
 // Hessian diagonal per row: h[m] = 2 sum_d F[d][m]^2 + 2 gamma L[m][m]
 hipError_t launch_setup_hdiag(const ProbView& pv, double* hdiag, hipStream_t s);
-// lambda = sqrt(sum_m w_m G_m^2), V_m = w_m G_m / lambda (w = null: all ones)
-hipError_t launch_power_normalize(double* G, double* V, int M, int ld, const double* w, double* lam_out,
-                                  hipStream_t s);
+// lambda = sqrt(sum_m w_m G_m^2), V_m = w_m G_m / lambda (w = null: all ones);
+// scratch: device [512] doubles
+hipError_t launch_power_normalize(double* G, double* V, int M, int ld, const double* w, double* scratch,
+                                  double* lam_out, hipStream_t s);
 hipError_t launch_reduce_sum(const double* partials, int n, double* out, hipStream_t s);
 template <typename Ts, typename Td>
 hipError_t launch_convert_pad(const Ts* src, Td* dst, long long rows, int cols, int ld_src, int ld_dst,

@@ -4,10 +4,12 @@
 // row projection and array fills.  The band-product kernels are in pdt_band.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 #include <type_traits>
 
+#include "pdt_decide.h"
 #include "pdt_device.h"
 #include "pdt_internal.h"
 #include "pdt_pmf.h"
@@ -17,87 +19,15 @@ namespace pdt {
 // ---------------------------------------------------------------------------------------
 // Fixed-order reduction of the partials and the accept/reject decision.
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ double block_sum256(double v, double* sh) {
-  const int tid = threadIdx.x;
-  sh[tid] = v;
-  __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if (tid < w) sh[tid] += sh[tid + w];
-    __syncthreads();
-  }
-  return sh[0];
-}
-
-__device__ __forceinline__ void decide_body(const double* partials, int n, SolverState* st, double* history,
-                                            int mode) {
-  __shared__ double sh[256];
-  if ((mode == DEC_ITER || mode == DEC_RESYNC) && st->done) return;
-  double s = 0.0;
-  for (int k = threadIdx.x; k < n; k += 256) s += partials[k];
-  const double f = block_sum256(s, sh);
-  if (threadIdx.x != 0) return;
-  if (mode == DEC_EVAL) {
-    st->f_eval = f;
-    return;
-  }
-  if (mode == DEC_RESYNC) {
-    // the exact objective of the current iterate replaces the one accumulated from
-    // FP32 updates, so later acceptance tests compare against the true value
-    st->f_cur = f;
-    st->f_new = f;
-    return;
-  }
-  if (mode == DEC_INIT) {
-    st->f_cur = f;
-    st->f_new = f;
-    st->t = 1.0;
-    st->beta = 0.0;
-    st->ix_cur = 0;
-    st->ix_prev = 0;
-    st->ix_new = 1;
-    st->sel_acc = 0;
-    st->iter = 0;
-    st->rejects = 0;
-    st->done = (st->max_iters <= 0) ||
-               (st->f_star > 0.0 && f - st->f_star <= st->rel_tol * st->f_star) ? 1 : 0;
-    return;
-  }
-  const double t = st->t;
-  const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
-  double tt;
-  st->f_new = f;
-  if (f <= st->f_cur) {
-    const int c = st->ix_cur, nw = st->ix_new;
-    st->ix_prev = c;
-    st->ix_cur = nw;
-    st->ix_new = 3 - c - nw;
-    st->f_cur = f;
-    st->sel_acc = 1;
-    tt = tn;
-  } else {
-    st->ix_prev = st->ix_cur;
-    st->sel_acc = 0;
-    st->rejects = st->rejects + 1;
-    tt = 1.0;
-  }
-  st->t = tt;
-  st->beta = (tt - 1.0) / (0.5 * (1.0 + sqrt(1.0 + 4.0 * tt * tt)));
-  const long long k = st->iter;
-  if (history) history[k] = st->f_cur;
-  st->iter = k + 1;
-  if (k + 1 >= st->max_iters) st->done = 1;
-  if (st->f_star > 0.0 && st->f_cur - st->f_star <= st->rel_tol * st->f_star) st->done = 1;
-}
-
 __global__ __launch_bounds__(256) void decide_kernel(const double* partials, int n, SolverState* st,
                                                      double* history, int mode) {
-  decide_body(partials, n, st, history, mode);
+  decide_body<256>(partials, n, st, history, mode);
 }
 
 template <typename TS>
 __global__ __launch_bounds__(256) void decide_batch_kernel(const BatchInst<TS>* insts, int mode) {
   const BatchInst<TS>& I = insts[blockIdx.x];
-  decide_body(I.b.partials, I.n_dt, I.st, I.b.history, mode);
+  decide_body<256>(I.b.partials, I.n_dt, I.st, I.b.history, mode);
 }
 
 __global__ __launch_bounds__(256) void reduce_sum_kernel(const double* partials, int n, double* out) {
@@ -220,19 +150,33 @@ __global__ __launch_bounds__(64) void project_rows_kernel(const T* X, T* Y, long
 }
 
 // power iteration on W^(1/2) H W^(1/2) with the iterate kept as u = W^(1/2) v:
-// lambda = sqrt(sum_m w_m G_m^2), V_m = w_m G_m / lambda (w = null: all ones)
-__global__ __launch_bounds__(256) void power_normalize_kernel(const double* G, double* V, int M, int ld,
-                                                              const double* w, double* lam_out) {
+// lambda = sqrt(sum_m w_m G_m^2), V_m = w_m G_m / lambda (w = null: all ones).  Two passes:
+// per-block partial sums over a fixed row partition, then every block forms lambda from
+// the partials in the same fixed order and scales its rows.
+constexpr int kNormBlocks = 512;
+
+__global__ __launch_bounds__(256) void power_partial_kernel(const double* G, int M, int ld, const double* w,
+                                                            double* partials) {
   __shared__ double sh[256];
   double s = 0.0;
-  for (int m = threadIdx.x; m < M; m += 256) {
+  for (long long m = (long long)blockIdx.x * 256 + threadIdx.x; m < M; m += (long long)gridDim.x * 256) {
     const double g = G[(size_t)m * ld];
     s += (w ? w[m] : 1.0) * g * g;
   }
+  const double t = block_sum256(s, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void power_scale_kernel(const double* G, double* V, int M, int ld, const double* w,
+                                                          const double* partials, int nb, double* lam_out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nb; k += 256) s += partials[k];
   const double lam = sqrt(block_sum256(s, sh));
   const double inv = lam > 0.0 ? 1.0 / lam : 0.0;
-  for (int m = threadIdx.x; m < M; m += 256) V[(size_t)m * ld] = (w ? w[m] : 1.0) * G[(size_t)m * ld] * inv;
-  if (threadIdx.x == 0) *lam_out = lam;
+  for (long long m = (long long)blockIdx.x * 256 + threadIdx.x; m < M; m += (long long)gridDim.x * 256)
+    V[(size_t)m * ld] = (w ? w[m] : 1.0) * G[(size_t)m * ld] * inv;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *lam_out = lam;
 }
 
 // Hessian diagonal of row m: 2 sum_d F[d][m]^2 over the probes whose band holds m (FP64
@@ -333,9 +277,11 @@ hipError_t launch_project_rows(const T* X, T* Y, long long rows, int cols, int l
   return hipGetLastError();
 }
 
-hipError_t launch_power_normalize(double* G, double* V, int M, int ld, const double* w, double* lam_out,
-                                  hipStream_t s) {
-  hipLaunchKernelGGL(power_normalize_kernel, dim3(1), dim3(256), 0, s, G, V, M, ld, w, lam_out);
+hipError_t launch_power_normalize(double* G, double* V, int M, int ld, const double* w, double* scratch,
+                                  double* lam_out, hipStream_t s) {
+  const int nb = std::max(1, std::min(kNormBlocks, (M + 255) / 256));
+  hipLaunchKernelGGL(power_partial_kernel, dim3(nb), dim3(256), 0, s, G, M, ld, w, scratch);
+  hipLaunchKernelGGL(power_scale_kernel, dim3(nb), dim3(256), 0, s, G, V, M, ld, w, scratch, nb, lam_out);
   return hipGetLastError();
 }
 

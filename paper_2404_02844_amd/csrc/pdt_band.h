@@ -72,6 +72,14 @@ constexpr int PF = 4;   // prefetch depth in contraction steps
 // first four waves finish the tile's 16 rows in the epilogues.
 
 // sum the KS partial 16 x (16 NT) tiles of a workgroup into S (LDS, row stride ld)
+// Orders one wave's LDS accesses for the compiler (the hardware already completes them in
+// issue order within a wave).
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename T, int NT, int KS, typename AccT>
 __device__ __forceinline__ void reduce_tiles(const AccT (&acc)[NT], double* S, int ld, int wv, int i, int kq) {
   for (int w = 0; w < KS; ++w) {
@@ -340,11 +348,14 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
     for (int j = 0; j < 16; ++j) vals[j] = gen_step(g, j);
     gn = gen_params(dc + stride);
   }
+  // Each wave stages only its own Ft[wv] slice, so the waves need no barrier between
+  // rounds: a wave's LDS operations complete in issue order, and wave_lds_order() keeps
+  // the compiler from moving them across each other.
   for (int rd = 0; rd < rounds; ++rd, dc += stride) {
     const int dcn = dc + stride;
 #pragma unroll
     for (int j = 0; j < 16; ++j) Ft[wv][lane][j] = vals[j];
-    __syncthreads();
+    wave_lds_order();
     // the next chunk's F values are generated between this chunk's MFMAs
     Gen g = gn;
 #pragma unroll
@@ -360,8 +371,9 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
     }
     vals[14] = gen_step(g, 14);
     vals[15] = gen_step(g, 15);
-    __syncthreads();
+    wave_lds_order();
   }
+  __syncthreads();  // S shares its LDS with every wave's Ft slice
   reduce_tiles<TC, NT, KS>(acc, S, LDT, wv, i, kq);
 
   // epilogue: wave wv finishes rows m0 + 4 wv + kq (one row per 16-lane group)

@@ -160,6 +160,20 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
   const int c0 = (nch * wv) / KS;
   const int c1 = (nch * (wv + 1)) / KS;
   const double mu4 = (mu * mu) * (mu * mu);
+  // Anchor of the first chunk whose photon numbers come within reach of this lane's band
+  // (ma + 60 >= lo_d, ma <= hi_d), evaluated before any X row is in flight: inside the
+  // loop the evaluation's registers would force the prefetched loads to drain.
+  int cb = -1;
+  double p_start = 0.0;
+  {
+    const int need = blo - 60 - kq - mlo;
+    int cs = need <= 0 ? 0 : (need + kChunkM - 1) / kChunkM;
+    cs = cs > c0 ? cs : c0;
+    if (cs < c1 && mlo + kChunkM * cs + kq <= bhi) {
+      cb = cs;
+      p_start = poisson_pmf(mlo + kChunkM * cs + kq, mu);
+    }
+  }
   TC xb[PF][NT];
   double rb[PF];
   if (c0 < c1) {
@@ -171,7 +185,12 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
     const int mb = mlo + kChunkM * c;
     const bool more = c + 1 < c1;
     const int ma = mb + kq;
-    if ((p == 0.0 || ((c - c0) & 15) == 0) && ma <= bhi && ma + 60 >= blo) p = poisson_pmf(ma, mu);
+    if (c == cb) {
+      p = p_start;
+    } else if ((p == 0.0 || ((c - c0) & 15) == 0) && ma <= bhi && ma + 60 >= blo) {
+      // a 16-chunk refresh, or a first value that underflowed (dense rows of bright probes)
+      p = poisson_pmf(ma, mu);
+    }
 #pragma unroll
     for (int st = 0; st < 16; ++st) {
       const int m = ma + 4 * st;

@@ -161,17 +161,23 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
   const int c1 = (nch * (wv + 1)) / KS;
   const double mu4 = (mu * mu) * (mu * mu);
   // Anchor of the first chunk whose photon numbers come within reach of this lane's band
-  // (ma + 60 >= lo_d, ma <= hi_d), evaluated before any X row is in flight: inside the
-  // loop the evaluation's registers would force the prefetched loads to drain.
+  // (ma + 60 >= lo_d, ma <= hi_d) and whose value does not underflow (dense rows of bright
+  // probes), evaluated before any X row is in flight: inside the loop the evaluation's
+  // registers would force the prefetched loads to drain.
   int cb = -1;
   double p_start = 0.0;
   {
     const int need = blo - 60 - kq - mlo;
     int cs = need <= 0 ? 0 : (need + kChunkM - 1) / kChunkM;
     cs = cs > c0 ? cs : c0;
-    if (cs < c1 && mlo + kChunkM * cs + kq <= bhi) {
-      cb = cs;
-      p_start = poisson_pmf(mlo + kChunkM * cs + kq, mu);
+#pragma unroll 1
+    for (int c = cs; c < c1 && mlo + kChunkM * c + kq <= bhi; ++c) {
+      const double v = poisson_pmf(mlo + kChunkM * c + kq, mu);
+      if (v > 0.0) {
+        cb = c;
+        p_start = v;
+        break;
+      }
     }
   }
   TC xb[PF][NT];
@@ -181,27 +187,32 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
     for (int q = 0; q < PF; ++q) load_step(mlo + kChunkM * c0 + 4 * q + kq, xb[q], rb[q]);
   }
   double p = 0.0;
-  for (int c = c0; c < c1; ++c) {
-    const int mb = mlo + kChunkM * c;
-    const bool more = c + 1 < c1;
-    const int ma = mb + kq;
-    if (c == cb) {
-      p = p_start;
-    } else if ((p == 0.0 || ((c - c0) & 15) == 0) && ma <= bhi && ma + 60 >= blo) {
-      // a 16-chunk refresh, or a first value that underflowed (dense rows of bright probes)
-      p = poisson_pmf(ma, mu);
+  // blocks of 16 chunks; the recursion restarts from an exact anchor at each block after
+  // the band-start chunk, which bounds the growth of its rounding error
+#pragma unroll 1
+  for (int cblk = c0; cblk < c1; cblk += 16) {
+    if (cb >= 0 && cblk > cb) {
+      const int ma = mlo + kChunkM * cblk + kq;
+      if (ma <= bhi && ma + 60 >= blo) p = poisson_pmf(ma, mu);
     }
+    const int cend = cblk + 16 < c1 ? cblk + 16 : c1;
+    for (int c = cblk; c < cend; ++c) {
+      const int mb = mlo + kChunkM * c;
+      const bool more = c + 1 < c1;
+      const int ma = mb + kq;
+      if (c == cb) p = p_start;
 #pragma unroll
-    for (int st = 0; st < 16; ++st) {
-      const int m = ma + 4 * st;
-      double f = (m >= blo && m <= bhi) ? p : 0.0;
-      f = (m == lumpm && m >= blo && m <= bhi) ? tl : f;
-      p *= mu4 * rb[st % PF];
-      const TC a = (TC)f;
+      for (int st = 0; st < 16; ++st) {
+        const int m = ma + 4 * st;
+        double f = (m >= blo && m <= bhi) ? p : 0.0;
+        f = (m == lumpm && m >= blo && m <= bhi) ? tl : f;
+        p *= mu4 * rb[st % PF];
+        const TC a = (TC)f;
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) acc[nt] = Acc<TC>::mfma(a, xb[st % PF][nt], acc[nt]);
-      if (st + PF < 16) load_step(m + 4 * PF, xb[st % PF], rb[st % PF]);
-      else if (more) load_step(m + 4 * PF, xb[st % PF], rb[st % PF]);
+        for (int nt = 0; nt < NT; ++nt) acc[nt] = Acc<TC>::mfma(a, xb[st % PF][nt], acc[nt]);
+        if (st + PF < 16) load_step(m + 4 * PF, xb[st % PF], rb[st % PF]);
+        else if (more) load_step(m + 4 * PF, xb[st % PF], rb[st % PF]);
+      }
     }
   }
   reduce_tiles<TC, NT, KS>(acc, S, LDT, wv, i, kq);

@@ -186,6 +186,39 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
 #pragma unroll
     for (int q = 0; q < PF; ++q) load_step(mlo + kChunkM * c0 + 4 * q + kq, xb[q], rb[q]);
   }
+
+  // Work of the epilogue that does not depend on the contraction is done here so that its
+  // loads overlap the main loop: the regulariser over this workgroup's slice of row
+  // pairs, and (when registers allow) O_cur and P of this group's output row.
+  double reg = 0.0;
+  if (pv.gamma != 0.0 && M > 1) {
+    const long long pairs = (long long)(M - 1);
+    const long long W = ntiles;
+    const long long per = (pairs + W - 1) / W;
+    const long long r0 = (long long)tile * per;
+    const long long r1 = r0 + per < pairs ? r0 + per : pairs;
+    const long long cnt = (r1 > r0 ? r1 - r0 : 0) * (long long)N;
+    for (long long q = tid; q < cnt; q += 64 * KS) {
+      const long long mm = r0 + q / N;
+      const int n = (int)(q % N);
+      const double e = (double)X[mm * Npad + n] - (double)X[(mm + 1) * Npad + n];
+      reg += e * e;
+    }
+  }
+  const int dd = d0 + 4 * wv + kq;  // epilogue row of this 16-lane group
+  const bool dval_e = wv < 4 && dd < D;
+  constexpr bool kHoist = NT >= 4 && NT <= 5;
+  T hoc[NT], hp[NT];
+  if constexpr (kHoist) {
+    if (dval_e) {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const size_t off = (size_t)dd * Npad + nt * 16 + i;
+        hoc[nt] = iter ? Ocur[off] : (T)0;
+        hp[nt] = b.P[off];
+      }
+    }
+  }
   double p = 0.0;
   // blocks of 16 chunks; the recursion restarts from an exact anchor at each block after
   // the band-start chunk, which bounds the growth of its rounding error
@@ -226,15 +259,20 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
     beta_acc = (T)((tn - 1.0) / tnn);
   }
   double part = 0.0;
-  const int dd = d0 + 4 * wv + kq;
-  if (wv < 4 && dd < D) {
+  if (dval_e) {
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const int n = nt * 16 + i;
       const size_t off = (size_t)dd * Npad + n;
-      const T oc_ = iter ? Ocur[off] : (T)0;
+      T oc_, pv_;
+      if constexpr (kHoist) {
+        oc_ = hoc[nt];
+        pv_ = hp[nt];
+      } else {
+        oc_ = iter ? Ocur[off] : (T)0;
+        pv_ = b.P[off];
+      }
       const T o = delta ? oc_ + (T)S[(4 * wv + kq) * LDT + n] : (T)S[(4 * wv + kq) * LDT + n];
-      const T pv_ = b.P[off];
       O[off] = o;
       if (n < N) {
         const double e = (double)o - (double)pv_;
@@ -256,23 +294,8 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
     }
   }
 
-  // regulariser over this workgroup's slice of row pairs
-  if (pv.gamma != 0.0 && M > 1) {
-    double reg = 0.0;
-    const long long pairs = (long long)(M - 1);
-    const long long W = ntiles;
-    const long long per = (pairs + W - 1) / W;
-    const long long r0 = (long long)tile * per;
-    const long long r1 = r0 + per < pairs ? r0 + per : pairs;
-    const long long cnt = (r1 > r0 ? r1 - r0 : 0) * (long long)N;
-    for (long long q = tid; q < cnt; q += 64 * KS) {
-      const long long m = r0 + q / N;
-      const int n = (int)(q % N);
-      const double e = (double)X[m * Npad + n] - (double)X[(m + 1) * Npad + n];
-      reg += e * e;
-    }
-    part += pv.gamma * reg;
-  }
+  // the regulariser partial formed before the main loop
+  if (pv.gamma != 0.0 && M > 1) part += pv.gamma * reg;
   part = group_sum<64>(part);
   if (lane == 0) red[wv] = part;
   __syncthreads();
@@ -369,6 +392,43 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
   TC rb[PF][NT];
 #pragma unroll
   for (int p = 0; p < PF; ++p) load_r(dc + 16 * kq + p, rb[p]);
+
+  // The epilogue's inputs that do not depend on the contraction -- Y = X + beta (X -
+  // X_prev) and its Laplacian along m for this group's row -- are loaded and formed here,
+  // so that their load latency overlaps the main loop (held in registers when the tile
+  // is narrow enough to leave room for them).
+  const int m = m0 + 4 * wv + kq;  // epilogue row of this 16-lane group
+  const bool mval = wv < 4 && m < M;
+  const T beta = (T)st->beta;
+  const T* __restrict__ Xc = b.X[st->ix_cur];
+  const T* __restrict__ Xp = b.X[st->ix_prev];
+  auto form_y = [&](int nt, T& xc, T& y, T& ly) {
+    const int n = nt * 16 + i;
+    xc = 0;
+    y = 0;
+    ly = 0;
+    if (mval && n < N) {
+      const size_t off = (size_t)m * Npad + n;
+      xc = Xc[off];
+      y = xc + beta * (xc - Xp[off]);
+      if (m > 0) {
+        const T xm = Xc[off - Npad];
+        ly += y - (xm + beta * (xm - Xp[off - Npad]));
+      }
+      if (m < M - 1) {
+        const T xq = Xc[off + Npad];
+        ly += y - (xq + beta * (xq - Xp[off + Npad]));
+      }
+    }
+  };
+  constexpr bool kHoist = NT >= 4 && NT <= 5;
+  T hx[NT], hy[NT], hly[NT];
+  if constexpr (kHoist) {
+    if (mode == FTR_STEP) {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) form_y(nt, hx[nt], hy[nt], hly[nt]);
+    }
+  }
   double vals[16];
   Gen gn;  // parameters of the chunk after the one being generated
   if (rounds > 0) {
@@ -407,13 +467,8 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
   reduce_tiles<TC, NT, KS>(acc, S, LDT, wv, i, kq);
 
   // epilogue: wave wv finishes rows m0 + 4 wv + kq (one row per 16-lane group)
-  const int m = m0 + 4 * wv + kq;
-  const bool mval = wv < 4 && m < M;
   const T g2 = (T)(2.0 * pv.gamma);
   if (mode == FTR_STEP) {
-    const T beta = (T)st->beta;
-    const T* __restrict__ Xc = b.X[st->ix_cur];
-    const T* __restrict__ Xp = b.X[st->ix_prev];
     T* __restrict__ Xn = b.X[st->ix_new];
     // row-scaled step: this group's row takes step * w_m
     const T stp = (T)((b.wrow && mval) ? step * b.wrow[m] : step);
@@ -424,22 +479,17 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const int n = nt * 16 + i;
+      T xc, y, ly;
+      if constexpr (kHoist) {
+        xc = hx[nt];
+        y = hy[nt];
+        ly = hly[nt];
+      } else {
+        form_y(nt, xc, y, ly);
+      }
+      xcs[nt] = xc;
       T zz = (n < N) ? (T)0 : neg_huge<T>();
-      xcs[nt] = 0;
       if (mval && n < N) {
-        const size_t off = (size_t)m * Npad + n;
-        const T xc = Xc[off];
-        xcs[nt] = xc;
-        const T y = xc + beta * (xc - Xp[off]);
-        T ly = 0;
-        if (m > 0) {
-          const T xm = Xc[off - Npad];
-          ly += y - (xm + beta * (xm - Xp[off - Npad]));
-        }
-        if (m < M - 1) {
-          const T xq = Xc[off + Npad];
-          ly += y - (xq + beta * (xq - Xp[off + Npad]));
-        }
         const T g = (T)2 * (T)S[(4 * wv + kq) * LDT + n] + g2 * ly;
         zz = y - stp * g;
       }
@@ -458,7 +508,6 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
     }
   } else {
     // gradient at X_cur (R_rej = F X_cur - P) and the KKT residual partial
-    const T* __restrict__ Xc = b.X[st->ix_cur];
     double part = 0.0;
     T g[NT], x[NT];
     T gmin = FLT_MAX;

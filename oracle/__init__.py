@@ -20,6 +20,10 @@ What it computes (arXiv 2404.02844):
                    problems, and the POVM fidelity of Eq. fidelities.
 * ``mlp``       -- FP64 forward/backward of the warm-start network and its input
                    resampling.
+* ``newton``    -- the paper's two-stage two-metric projected truncated Newton method
+                   (App. B, Algorithms 1-3).
+* ``smoothing`` -- the long-range average of Eq. smoothing used before the paper's
+                   stage-2-only second run.
 
 Every reduction is FP64.  Functions cite the passage they follow.
 """

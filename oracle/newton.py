@@ -33,7 +33,10 @@ Readings where the paper is silent (also listed in the design notes):
     stage 2 it is exact: the bound projection moves entry (i, n) by P unless
     Pi[i][n] = 0 and P < 0;
   * a direction that is not a descent direction (phi'(0) >= 0) is replaced by -g;
-  * at most 60 line-search trials (beta^60 ~ 3e-8).
+  * at most 60 line-search trials (beta^60 ~ 3e-8);
+  * a zero Hessian diagonal entry (a row no probe reaches, gamma = 0) is taken as 1 in
+    the preconditioner and in the diagonal block of the bound entries;
+  * stage2_only=True starts in stage 2 (the comparison of App. B's convergence study).
 """
 from __future__ import annotations
 
@@ -86,7 +89,7 @@ def stage1_direction(F, gamma: float, Pi: np.ndarray, g: np.ndarray, h: np.ndarr
     """Two-metric Newton direction on the simplex rows (Algorithm 2)."""
     bind = (Pi <= eps) & (g > 0)
     free = ~bind
-    hd = np.broadcast_to(h[:, None], Pi.shape)
+    hd = np.broadcast_to(np.where(h > 0, h, 1.0)[:, None], Pi.shape)
 
     def apply_D(v):
         return np.where(free, hessian_apply(F, gamma, np.where(free, v, 0.0)), 0.0) + np.where(bind, hd * v, 0.0)
@@ -133,7 +136,7 @@ def stage2_direction(F, gamma: float, Pi: np.ndarray, g: np.ndarray, h: np.ndarr
     var[rows, mi] = False
     bind = var & (Pi <= eps) & (gr > 0)
     free = var & ~bind
-    hd = np.broadcast_to(2.0 * h[:, None], Pi.shape)
+    hd = np.broadcast_to(np.where(h > 0, 2.0 * h, 1.0)[:, None], Pi.shape)
 
     def apply_D(v):
         w = contract(hessian_apply(F, gamma, expand(np.where(free, v, 0.0), mi)), mi)
@@ -180,14 +183,14 @@ def binding_eps_stage2(Pi: np.ndarray, g: np.ndarray, mi: np.ndarray) -> float:
 
 def two_stage(F, P: np.ndarray, gamma: float, *, max_newton: int = 200, eps_kkt: float = 1e-10,
               stage_switch: float = 1e-4, cg_rtol: float = 1e-4, cg_max: int = 50,
-              X0: np.ndarray | None = None) -> NewtonResult:
+              X0: np.ndarray | None = None, stage2_only: bool = False) -> NewtonResult:
     M = F.shape[1]
     N = P.shape[1]
     X = project_rows(np.full((M, N), 1.0 / N) if X0 is None else X0)
     h = hessian_diag(F, gamma, M)
     f = objective(F, P, X, gamma, exact=False)
     hist = [f]
-    stage = 1
+    stage = 2 if stage2_only else 1
     n1 = n2 = cg_total = 0
     for _ in range(max_newton):
         g = gradient(F, P, X, gamma)

@@ -149,3 +149,14 @@ def test_two_stage_reaches_the_certified_optimum():
     assert (r.f - fstar) <= 1e-8 * fstar and r.f >= fstar * (1 - 1e-14)
     assert np.max(np.abs(r.X - np.array(gold["Pi_star"]))) <= 1e-4
     assert np.all(r.X >= 0) and np.max(np.abs(r.X.sum(axis=1) - 1)) <= 1e-13
+
+
+def test_stage2_only_reaches_the_same_optimum():
+    inst = synth.c1_small()
+    F, _, _ = poisson.build_F(inst.mu, inst.M, inst.threshold, inst.tail_mode)
+    with open(os.path.join(GOLDEN, "c1_oracle.json")) as fh:
+        fstar = json.load(fh)["f_star"]
+    r = newton.two_stage(F, inst.P, inst.gamma, max_newton=300, eps_kkt=1e-13, stage2_only=True)
+    assert r.stage1_iters == 0 and r.stage2_iters >= 1
+    assert np.all(np.diff(r.history) <= 0)
+    assert (r.f - fstar) <= 1e-7 * fstar

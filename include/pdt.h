@@ -178,6 +178,18 @@ pdt_status pdt_kkt(pdt_problem_t problem, const double* Pi, double* kkt_out);
  */
 pdt_status pdt_project_simplex(const double* X, double* Y, int64_t rows, int64_t cols, void* stream);
 
+/*
+ * Long-range smoothing before the paper's second, stage-2-only run (Sec. 3.2,
+ * Eq. smoothing): out[i] = mean of Pi rows i - h .. i + h with h = min(floor(i /
+ * divisor), M - 1 - i) (the paper: divisor 50), for i >= skip (the paper: ~100); rows
+ * below skip are copied.  The window stays centred on i, shrinking at the top of the
+ * range.  Pi, out: device [M*N] row-major FP64 (out == Pi allowed).  Window sums are
+ * differences of compensated FP64 column prefix sums (temporary device memory of
+ * 2 (M + 1 + M/256) N doubles).  stream: hipStream_t or NULL.
+ */
+pdt_status pdt_smooth_rows(const double* Pi, double* out, int64_t M, int64_t N, int32_t divisor, int64_t skip,
+                           void* stream);
+
 /* Same, FP32. */
 pdt_status pdt_project_simplex_f32(const float* X, float* Y, int64_t rows, int64_t cols, void* stream);
 
@@ -203,6 +215,80 @@ pdt_status pdt_problem_scaling(pdt_problem_t problem, double* hdiag, double* lip
 pdt_status pdt_problem_set_tiles(pdt_problem_t problem, int64_t instance, int precision, int ks_fx, int ks_ftr);
 /* The shape in effect (host int* outputs, nullable). */
 pdt_status pdt_problem_tiles(pdt_problem_t problem, int64_t instance, int precision, int* ks_fx, int* ks_ftr);
+
+/*
+ * The paper's own solver: the two-stage two-metric projected truncated Newton method
+ * of App. B (Algorithms 1-3) on instance 0.
+ *
+ * Stage 1 (Algorithm 2): binding set I = {Pi <= eps, df/dPi > 0} (Eq. 2metric_I) with
+ * eps = min(1e-3, ||Pi - P_S(Pi - grad)||); direction from D P = -grad, D the Hessian
+ * 2 F^T F + 2 gamma L_path on the free entries and its diagonal on I, solved by
+ * conjugate gradients preconditioned with the Hessian diagonal (Hessian products are
+ * the band kernels of pdt_solve); Armijo search (beta 3/4, c 1/10) on
+ * P_S(Pi + alpha P), slope phi'(0) the exact one-sided derivative of that path (the
+ * projection of P onto the tangent cone of the simplex rows).
+ * Switches to stage 2 once |phi'(0)| <= stage_switch (or when no trial is accepted).
+ * Stage 2 (Algorithm 1): every row's largest entry m(i) is eliminated through the row
+ * sum; the same two-metric step in the reduced variables (reduced Hessian T^T H T,
+ * diagonal 2 h), trials max(Pi + alpha P, 0) with the eliminated entry from the sum,
+ * accepted when Armijo holds and every eliminated entry is >= 0.  Stops once the KKT
+ * residual with the clamped multiplier max(0, -min_n grad) is <= eps_kkt, or when no
+ * trial is accepted.  A descent test failure (phi'(0) >= 0) falls back to -grad.
+ *
+ * Pi: device [M*N] row-major FP64, read when init == PDT_INIT_USER (projected onto the
+ * simplex rows first), always overwritten with the final iterate.  history: host
+ * [max_newton + 1] (nullable), f at the start and after every Newton step.
+ * With f_star > 0 the solve also stops once f - f_star <= rel_obj_tol * f_star (the
+ * comparison test of pdt_solve).  Returns PDT_ERR_NOT_CONVERGED (with Pi and info
+ * filled) when the method stopped (max_newton reached, or no stage-2 trial accepted)
+ * before either test held.
+ */
+typedef struct {
+  int64_t max_newton;     /* Newton steps of both stages, >= 0 */
+  double eps_kkt;         /* stage-2 stopping residual, >= 0 */
+  double stage_switch;    /* |phi'(0)| of the stage transition (paper: 1e-4) */
+  double cg_rtol;         /* CG stops at ||r|| <= cg_rtol ||r_0|| */
+  int32_t cg_max;         /* CG iterations per Newton step, >= 1 */
+  int32_t init;           /* PDT_INIT_UNIFORM or PDT_INIT_USER */
+  int32_t stage2_only;    /* 1: start in stage 2 */
+  double* history;        /* host [max_newton + 1] or NULL */
+  double f_star;          /* known optimum value; <= 0 disables the objective test */
+  double rel_obj_tol;     /* also stop once f - f_star <= rel_obj_tol * f_star */
+} pdt_newton_opts;
+
+typedef struct {
+  int64_t stage1_iters;   /* accepted or attempted stage-1 steps */
+  int64_t stage2_iters;
+  int64_t cg_iters;       /* CG iterations over all steps */
+  int64_t line_trials;    /* objective evaluations of the line searches */
+  double objective;       /* f at the returned Pi */
+  double kkt;             /* KKT residual with the clamped multiplier */
+  double seconds;
+  int converged;          /* 1 if the KKT or the objective test was met */
+} pdt_newton_info;
+
+pdt_status pdt_newton_solve(pdt_problem_t problem, double* Pi, const pdt_newton_opts* opts,
+                            pdt_newton_info* info);
+
+/*
+ * Hessian product HV = 2 F^T (F V) + 2 gamma L_path V of instance 0 (Table "ops",
+ * Hessian products: the operator of the CG solves), by the band kernels.  V, HV: device [M*N]
+ * row-major FP64 (distinct).
+ */
+pdt_status pdt_hessian_apply(pdt_problem_t problem, const double* V, double* HV);
+
+/*
+ * One Newton direction of the given stage (1 or 2) at Pi (device [M*N], used as given)
+ * with binding tolerance eps >= 0: the CG solve of the two-metric system described at
+ * pdt_newton_solve.  Dir: device [M*N], receives the direction (stage 2: the reduced
+ * variables, 0 at the eliminated entries).  row_max: device int32 [M] (nullable),
+ * receives m(i) in stage 2.  cg_iters, slope (host, nullable): CG iterations and
+ * phi'(0) of the direction as the line search would use it.  No steepest-descent
+ * fallback is applied.
+ */
+pdt_status pdt_newton_direction(pdt_problem_t problem, int stage, const double* Pi, double eps, double cg_rtol,
+                                int32_t cg_max, double* Dir, int32_t* row_max, int64_t* cg_iters,
+                                double* slope);
 
 /*
  * Warm-start network (learned initial Pi; not in the paper, whose runs start from

@@ -28,10 +28,14 @@ Readings where the paper is silent (also listed in the design notes):
     projected-gradient residual: ||Pi - P_{S^M}[Pi - g]|| in stage 1, and
     ||min(Pi, g_reduced)|| over the reduced variables in stage 2;
   * CG: from P = 0, stops at ||r|| <= cg_rtol ||rhs|| (1e-4) or after cg_max (50) steps;
-  * phi'(0) in stage 1 is the one-sided difference quotient at alpha0 = 1e-9 (the
-    projection is piecewise linear in alpha, so the quotient is its slope at 0); in
-    stage 2 it is exact: the bound projection moves entry (i, n) by P unless
-    Pi[i][n] = 0 and P < 0;
+  * phi'(0) is the exact one-sided derivative at alpha = 0.  In stage 1, for a row x on
+    the simplex, P_S(x + alpha d) = max(x + alpha d - alpha t, 0) for small alpha > 0,
+    where t solves sum_{x_n > 0} (d_n - t) + sum_{x_n = 0} max(d_n - t, 0) = 0; the
+    path's derivative is v_n = d_n - t on the support and max(d_n - t, 0) off it (the
+    projection of d onto the tangent cone of the simplex at x).  In stage 2 the bound
+    projection moves entry (i, n) by P unless Pi[i][n] = 0 and P < 0.  (A difference
+    quotient carries rounding noise of ~1e-7 of X per entry at alpha = 1e-9, which
+    decides the stage switch once |phi'(0)| is small.);
   * a direction that is not a descent direction (phi'(0) >= 0) is replaced by -g;
   * at most 60 line-search trials (beta^60 ~ 3e-8);
   * a zero Hessian diagonal entry (a row no probe reaches, gamma = 0) is taken as 1 in
@@ -52,7 +56,6 @@ from .simplex import project_rows
 
 BETA = 0.75
 C_ARMIJO = 0.1
-ALPHA0 = 1e-9
 MAX_TRIALS = 60
 
 
@@ -98,9 +101,25 @@ def stage1_direction(F, gamma: float, Pi: np.ndarray, g: np.ndarray, h: np.ndarr
     return P, it, bind
 
 
+def tangent_direction(x: np.ndarray, d: np.ndarray) -> np.ndarray:
+    """d/dalpha P_S(x + alpha d) at alpha = 0+ for one row x on the simplex: the shift t
+    over the support and the zero entries whose d_n exceeds it, found by growing the
+    threshold until the set of entries above it stops changing (each pass can only
+    drop entries, so it ends after at most N passes)."""
+    zero = x == 0.0
+    active = np.ones(x.shape, dtype=bool)
+    while True:
+        t = float(np.sum(d[active])) / int(np.count_nonzero(active))
+        keep = ~zero | (d > t)
+        if np.array_equal(keep & active, active):
+            break
+        active &= keep
+    return np.where(zero, np.maximum(d - t, 0.0), d - t)
+
+
 def stage1_slope(Pi: np.ndarray, P: np.ndarray, g: np.ndarray) -> float:
-    d = (project_rows(Pi + ALPHA0 * P) - Pi) / ALPHA0
-    return float(np.sum(g * d))
+    v = np.stack([tangent_direction(Pi[i], P[i]) for i in range(Pi.shape[0])])
+    return float(np.sum(g * v))
 
 
 def reduce_max(Pi: np.ndarray) -> np.ndarray:

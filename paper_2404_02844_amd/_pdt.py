@@ -65,6 +65,22 @@ class pdt_solve_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class pdt_newton_opts(ctypes.Structure):
+    _fields_ = [("max_newton", ctypes.c_int64), ("eps_kkt", ctypes.c_double), ("stage_switch", ctypes.c_double),
+                ("cg_rtol", ctypes.c_double), ("cg_max", ctypes.c_int32), ("init", ctypes.c_int32),
+                ("stage2_only", ctypes.c_int32), ("history", ctypes.c_void_p), ("f_star", ctypes.c_double),
+                ("rel_obj_tol", ctypes.c_double)]
+
+
+class pdt_newton_info(ctypes.Structure):
+    _fields_ = [("stage1_iters", ctypes.c_int64), ("stage2_iters", ctypes.c_int64), ("cg_iters", ctypes.c_int64),
+                ("line_trials", ctypes.c_int64), ("objective", ctypes.c_double), ("kkt", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("converged", ctypes.c_int)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -106,6 +122,13 @@ def lib() -> ctypes.CDLL:
         L.pdt_solve_batch.argtypes = [vp, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(pdt_solve_opts), dp,
                                       ctypes.POINTER(pdt_solve_info)]
         L.pdt_solve_batch.restype = ctypes.c_int
+        L.pdt_newton_solve.argtypes = [vp, vp, ctypes.POINTER(pdt_newton_opts), ctypes.POINTER(pdt_newton_info)]
+        L.pdt_hessian_apply.argtypes = [vp, vp, vp]
+        L.pdt_newton_direction.argtypes = [vp, ctypes.c_int, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                           vp, vp, ctypes.POINTER(ctypes.c_int64), dp]
+        L.pdt_smooth_rows.argtypes = [vp, vp, i64, i64, ctypes.c_int32, i64, vp]
+        for name in ("pdt_newton_solve", "pdt_hessian_apply", "pdt_newton_direction", "pdt_smooth_rows"):
+            getattr(L, name).restype = ctypes.c_int
         L.pdt_last_error.argtypes = []
         L.pdt_last_error.restype = ctypes.c_char_p
         for name in ("pdt_make_problem", "pdt_solve", "pdt_objective", "pdt_kkt", "pdt_project_simplex",
@@ -204,6 +227,53 @@ def pdt_kkt(handle, Pi) -> float:
     return k.value
 
 
+def pdt_newton_solve(handle, Pi, *, max_newton=200, eps_kkt=1e-10, stage_switch=1e-4, cg_rtol=1e-4, cg_max=50,
+                     init=PDT_INIT_UNIFORM, stage2_only=False, history=None, f_star=0.0, rel_obj_tol=0.0,
+                     allow_not_converged=True) -> dict:
+    """Two-stage Newton solve in place: ``Pi`` is a contiguous float64 [M, N] GPU tensor.
+    ``history``: optional float64 numpy array of at least max_newton + 1 entries."""
+    import numpy as np
+    if history is not None and (history.dtype != np.float64 or history.size < max_newton + 1
+                                or not history.flags["C_CONTIGUOUS"]):
+        raise ValueError("history must be a contiguous float64 array of max_newton + 1 entries")
+    o = pdt_newton_opts(max_newton=int(max_newton), eps_kkt=float(eps_kkt), stage_switch=float(stage_switch),
+                        cg_rtol=float(cg_rtol), cg_max=int(cg_max), init=int(init), stage2_only=int(bool(stage2_only)),
+                        history=history.ctypes.data_as(ctypes.c_void_p) if history is not None else None,
+                        f_star=float(f_star), rel_obj_tol=float(rel_obj_tol))
+    info = pdt_newton_info()
+    st = _check(lib().pdt_newton_solve(handle, ctypes.c_void_p(Pi.data_ptr()), ctypes.byref(o), ctypes.byref(info)),
+                allow=(PDT_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+    d = info.as_dict()
+    d["status"] = st
+    return d
+
+
+def pdt_hessian_apply(handle, V, HV) -> None:
+    """HV = H V for contiguous float64 [M, N] GPU tensors."""
+    _check(lib().pdt_hessian_apply(handle, ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(HV.data_ptr())))
+
+
+def pdt_newton_direction(handle, stage: int, Pi, eps: float, cg_rtol: float, cg_max: int, Dir, row_max=None) -> dict:
+    """One Newton direction at ``Pi`` into ``Dir`` (float64 [M, N] GPU tensors); ``row_max``:
+    optional int32 [M] GPU tensor for the stage-2 row maxima."""
+    it = ctypes.c_int64()
+    sl = ctypes.c_double()
+    _check(lib().pdt_newton_direction(handle, int(stage), ctypes.c_void_p(Pi.data_ptr()), float(eps),
+                                      float(cg_rtol), int(cg_max), ctypes.c_void_p(Dir.data_ptr()),
+                                      ctypes.c_void_p(row_max.data_ptr()) if row_max is not None else None,
+                                      ctypes.byref(it), ctypes.byref(sl)))
+    return {"cg_iters": it.value, "slope": sl.value}
+
+
+def pdt_smooth_rows(Pi, out=None, divisor: int = 50, skip: int = 100, stream=None):
+    """Long-range smoothing of a contiguous float64 [M, N] GPU tensor (Eq. smoothing)."""
+    if out is None:
+        out = Pi.new_empty(Pi.shape)
+    _check(lib().pdt_smooth_rows(ctypes.c_void_p(Pi.data_ptr()), ctypes.c_void_p(out.data_ptr()), int(Pi.shape[0]),
+                                 int(Pi.shape[1]), int(divisor), int(skip), _stream_ptr(stream)))
+    return out
+
+
 def pdt_project_simplex(X, Y=None, stream=None):
     """Row-wise simplex projection of a 2-D float64 or float32 GPU tensor."""
     if Y is None:
@@ -274,6 +344,15 @@ class Problem:
 
     def bands(self):
         return pdt_problem_bands(self.handle, self.D)
+
+    def newton(self, Pi, **kw):
+        return pdt_newton_solve(self.handle, Pi, **kw)
+
+    def hessian(self, V, HV):
+        pdt_hessian_apply(self.handle, V, HV)
+
+    def newton_direction(self, stage, Pi, eps, cg_rtol, cg_max, Dir, row_max=None):
+        return pdt_newton_direction(self.handle, stage, Pi, eps, cg_rtol, cg_max, Dir, row_max)
 
     def scaling(self):
         return pdt_problem_scaling(self.handle, self.M)

@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdt.so")
 SOURCES = ["pdt_band_f64.hip", "pdt_band_f32.hip", "pdt_band_mixed.hip", "pdt_band_batch.hip",
-           "pdt_kernels.hip", "pdt_mlp.hip", "pdt_capi.hip"]
+           "pdt_kernels.hip", "pdt_newton.hip", "pdt_smooth.hip", "pdt_mlp.hip", "pdt_capi.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # keep packed FP32 instructions out of every kernel
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

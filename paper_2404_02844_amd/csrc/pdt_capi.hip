@@ -14,6 +14,7 @@
 
 #include "pdt.h"
 #include "pdt_internal.h"
+#include "pdt_newton.h"
 #include "pdt_tuning.h"
 #include "pdt_mlp.h"
 
@@ -77,6 +78,31 @@ struct Work {
   bool ready = false;
 };
 
+// Buffers of the Newton solver ([M][Npad] unless noted), allocated on first use.
+struct NewtonWork {
+  bool ready = false;
+  double* Dir = nullptr;  // Newton direction (stage 2: reduced variables)
+  double* res = nullptr;  // CG residual
+  double* z = nullptr;    // preconditioned residual
+  double* p = nullptr;    // CG search direction
+  double* q = nullptr;    // D p
+  double* Vf = nullptr;   // free part of p (stage 2: expanded by T), the Hessian's operand
+  double* Gh = nullptr;   // H Vf
+  double* G = nullptr;    // gradient at the current iterate
+  double* Oh = nullptr;   // [D][Npad] F Vf
+  double* Rh = nullptr;   // [D][Npad] F Vf (the transposed product's operand)
+  double* Pz = nullptr;   // [D][Npad] zeros: the data term of a Hessian product
+  double* Rg = nullptr;   // [D][Npad] F X - P of the last evaluated point
+  double* part = nullptr;  // [2 kNtBlocks] row-kernel partials
+  double* bpart = nullptr;  // band-kernel partials
+  uint8_t* mask = nullptr;
+  int* mi = nullptr;       // [M] row maxima of stage 2
+  NewtonState* ns = nullptr;
+  SolverState* st = nullptr;  // ix_cur = 0, never done: plain evaluations
+  int* flag_h = nullptr;      // pinned host [2]: CG completion flags
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
 struct Instance {
   int64_t M = 0, N = 0, D = 0, Npad = 0;
   double gamma = 0, tau = 0;
@@ -119,6 +145,7 @@ struct Instance {
   const double* graph_w[3] = {nullptr, nullptr, nullptr};
   // waves per workgroup forced per variant and kernel (0: from the tuning table)
   int ks_force[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  NewtonWork nw;
 };
 
 }  // namespace
@@ -613,6 +640,239 @@ void run_mixed(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double s
   out = h;
 }
 
+// ---------------------------------------------------------------------------------------
+// Two-stage two-metric projected truncated Newton method (App. B, Algorithms 1-3).
+// Host-driven: the host reads one scalar record per binding-set tolerance, slope and
+// line-search trial; the CG iterations run back to back on the device, each queued
+// before the completion flag of the previous one has been read.
+// ---------------------------------------------------------------------------------------
+constexpr double kNtBeta = 0.75;     // Armijo backtracking factor
+constexpr double kNtArmijo = 0.1;    // Armijo constant c
+constexpr int kNtMaxTrials = 60;     // beta^60 ~ 3e-8
+
+NewtonWork& ensure_newton(pdt_problem_s* pb, Instance& I) {
+  NewtonWork& nw = I.nw;
+  if (nw.ready) return nw;
+  Arena& A = pb->arena;
+  hipStream_t s = pb->stream;
+  const size_t xm = (size_t)I.M * I.Npad, od = (size_t)I.D * I.Npad;
+  nw.Dir = A.alloc<double>(xm);
+  nw.res = A.alloc<double>(xm);
+  nw.z = A.alloc<double>(xm);
+  nw.p = A.alloc<double>(xm);
+  nw.q = A.alloc<double>(xm);
+  nw.Vf = A.alloc<double>(xm);
+  nw.Gh = A.alloc<double>(xm);
+  nw.G = A.alloc<double>(xm);
+  nw.Oh = A.alloc<double>(od);
+  nw.Rh = A.alloc<double>(od);
+  nw.Pz = A.alloc<double>(od);
+  nw.Rg = A.alloc<double>(od);
+  nw.part = A.alloc<double>(2 * kNtBlocks);
+  nw.bpart = A.alloc<double>((size_t)I.n_partials);
+  nw.mask = A.alloc<uint8_t>(xm);
+  nw.mi = A.alloc<int>((size_t)I.M);
+  nw.ns = A.alloc<NewtonState>(1);
+  nw.st = A.alloc<SolverState>(1);
+  HIPCHK(hipMemsetAsync(nw.Pz, 0, od * sizeof(double), s));
+  HIPCHK(hipMemsetAsync(nw.mi, 0, (size_t)I.M * sizeof(int), s));
+  HIPCHK(hipMemsetAsync(nw.ns, 0, sizeof(NewtonState), s));
+  init_state(s, nw.st, 0, 0.0, 0.0);
+  if (!nw.flag_h) HIPCHK(hipHostMalloc((void**)&nw.flag_h, 2 * sizeof(int), hipHostMallocDefault));
+  for (hipEvent_t& e : nw.ev)
+    if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  nw.ready = true;
+  return nw;
+}
+
+// Band-kernel view of one array as the current iterate of a plain evaluation.
+Bufs<double> nt_bufs(const Instance& I, const NewtonWork& nw, const double* X, double* O, const double* P, double* R,
+                     double* G) {
+  Bufs<double> b;
+  for (int k = 0; k < 3; ++k) {
+    b.X[k] = const_cast<double*>(X);
+    b.O[k] = O;
+  }
+  b.P = P;
+  b.R_acc = R;
+  b.R_rej = R;
+  b.G = G;
+  b.partials = nw.bpart;
+  b.n_partials = I.n_partials;
+  b.history = nullptr;
+  return b;
+}
+
+// HV = 2 F^T (F V) + 2 gamma L V: forward product against zero data, then the transposed
+// product's gradient mode on the result.
+void nt_hessian(const ProbView& pv, const Instance& I, NewtonWork& nw, const double* V, double* HV, hipStream_t s) {
+  const Bufs<double> b = nt_bufs(I, nw, V, nw.Oh, nw.Pz, nw.Rh, HV);
+  HIPCHK(launch_fx<double>(pv, b, nw.st, FX_EVAL, s));
+  HIPCHK(launch_ftr<double>(pv, b, nw.st, FTR_GRAD, 0.0, s));
+}
+
+// f(X) into nw.st->f_eval and F X - P into nw.Rg (queued, not waited for)
+void nt_eval(const ProbView& pv, const Instance& I, NewtonWork& nw, const double* X, hipStream_t s) {
+  const Bufs<double> b = nt_bufs(I, nw, X, I.w64.O[0], I.P64, nw.Rg, nw.G);
+  HIPCHK(launch_fx<double>(pv, b, nw.st, FX_EVAL, s));
+  HIPCHK(launch_decide(nw.bpart, fx_num_waves(pv), nw.st, nullptr, DEC_EVAL, s));
+}
+
+// gradient at X into nw.G from the residual F X - P left in nw.Rg by nt_eval(X)
+void nt_gradient(const ProbView& pv, const Instance& I, NewtonWork& nw, const double* X, hipStream_t s) {
+  const Bufs<double> b = nt_bufs(I, nw, X, I.w64.O[0], I.P64, nw.Rg, nw.G);
+  HIPCHK(launch_ftr<double>(pv, b, nw.st, FTR_GRAD, 0.0, s));
+}
+
+NewtonState nt_read(hipStream_t s, const NewtonWork& nw, double* f_eval = nullptr) {
+  NewtonState h;
+  HIPCHK(hipMemcpyAsync(&h, nw.ns, sizeof(h), hipMemcpyDeviceToHost, s));
+  SolverState st;
+  if (f_eval) HIPCHK(hipMemcpyAsync(&st, nw.st, sizeof(st), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (f_eval) *f_eval = st.f_eval;
+  return h;
+}
+
+// Direction of one Newton step at X (gradient in nw.G): codes, CG solve, result in
+// nw.Dir (and the row maxima in nw.mi for stage 2).  Returns the CG iterations.
+int nt_direction(const ProbView& pv, const Instance& I, NewtonWork& nw, const NtRows& rows, const double* X,
+                 double eps, double rtol, int cg_max, hipStream_t s) {
+  HIPCHK(launch_nt_prep(rows, X, nw.G, I.hdiag, eps, nw.mask, nw.mi, nw.res, nw.z, nw.p, nw.Vf, nw.Dir, nw.part,
+                        nw.ns, rtol, cg_max, s));
+  for (int it = 0; it < cg_max; ++it) {
+    nt_hessian(pv, I, nw, nw.Vf, nw.Gh, s);
+    HIPCHK(launch_nt_q(rows, nw.mask, nw.mi, I.hdiag, nw.p, nw.Gh, nw.q, nw.part, nw.ns, s));
+    HIPCHK(launch_nt_update(rows, nw.mask, I.hdiag, nw.Dir, nw.res, nw.z, nw.p, nw.q, nw.part, nw.ns, s));
+    HIPCHK(launch_nt_dir(rows, nw.mask, nw.mi, nw.z, nw.p, nw.Vf, nw.ns, s));
+    const int slot = it & 1;
+    HIPCHK(hipMemcpyAsync(&nw.flag_h[slot], &nw.ns->cg_done, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(nw.ev[slot], s));
+    if (it >= 1) {
+      HIPCHK(hipEventSynchronize(nw.ev[slot ^ 1]));
+      if (nw.flag_h[slot ^ 1]) break;
+    }
+  }
+  return nt_read(s, nw).cg_iter;
+}
+
+double nt_slope(const Instance& I, NewtonWork& nw, const NtRows& rows, const double* X, hipStream_t s) {
+  HIPCHK(launch_nt_slope(rows, X, nw.Dir, nw.G, nw.mi, nw.part, nw.ns, s));
+  (void)I;
+  return nt_read(s, nw).out[0];
+}
+
+struct NewtonRun {
+  int64_t n1 = 0, n2 = 0, cg = 0, trials = 0;
+  double f = 0.0, kkt = 0.0;
+  bool converged = false;
+  std::vector<double> hist;
+};
+
+// Runs the method from the iterate in I.w64.X[0]; leaves the result there.
+void newton_run(pdt_problem_s* pb, Instance& I, const pdt_newton_opts& o, NewtonRun& out) {
+  hipStream_t s = pb->stream;
+  const ProbView pv = view_var(I, VAR_FP64);
+  NewtonWork& nw = ensure_newton(pb, I);
+  double* X = I.w64.X[0];
+  double* Xa = I.w64.X[1];
+  const double mn = (double)I.M * (double)I.N;
+  NtRows rows{(int)I.M, (int)I.N, (int)I.Npad, 1};
+  double f = 0.0;
+  nt_eval(pv, I, nw, X, s);
+  (void)nt_read(s, nw, &f);
+  out.hist.push_back(f);
+  int stage = o.stage2_only ? 2 : 1;
+  bool resid_ok = true;  // nw.Rg holds F X - P of the current X
+  double kkt = 0.0;
+  bool kkt_fresh = false;
+  for (int64_t k = 0; k < o.max_newton; ++k) {
+    if (!resid_ok) {
+      nt_eval(pv, I, nw, X, s);
+      resid_ok = true;
+    }
+    nt_gradient(pv, I, nw, X, s);
+    rows.stage = stage;
+    HIPCHK(launch_nt_measure(rows, X, nw.G, nw.part, nw.ns, s));
+    NewtonState m = nt_read(s, nw);
+    kkt = std::sqrt(m.out[0] / mn);
+    kkt_fresh = true;
+    if (stage == 2 && kkt <= o.eps_kkt) {
+      out.converged = true;
+      break;
+    }
+    const double eps = std::min(1e-3, std::sqrt(m.out[1]));
+    out.cg += nt_direction(pv, I, nw, rows, X, eps, o.cg_rtol, o.cg_max, s);
+    double slope = nt_slope(I, nw, rows, X, s);
+    if (slope >= 0.0) {
+      HIPCHK(launch_nt_negrad(rows, nw.G, nw.mi, nw.Dir, s));
+      slope = nt_slope(I, nw, rows, X, s);
+    }
+    if (stage == 1 && std::fabs(slope) <= o.stage_switch) {
+      stage = 2;
+      continue;
+    }
+    if (stage == 2 && slope == 0.0) break;
+    if (stage == 1) ++out.n1;
+    else ++out.n2;
+    double a = 1.0;
+    bool accepted = false;
+    for (int t = 0; t < kNtMaxTrials; ++t) {
+      HIPCHK(launch_nt_trial(rows, X, nw.Dir, nw.mi, a, Xa, nw.part, nw.ns, s));
+      nt_eval(pv, I, nw, Xa, s);
+      double fa = 0.0;
+      const NewtonState tr = nt_read(s, nw, &fa);
+      ++out.trials;
+      const bool ok = stage == 1 || tr.out[1] == 0.0;
+      if (ok && fa <= f + kNtArmijo * a * slope) {
+        std::swap(X, Xa);
+        f = fa;
+        accepted = true;
+        break;
+      }
+      a *= kNtBeta;
+    }
+    resid_ok = accepted;
+    kkt_fresh = false;
+    out.hist.push_back(f);
+    if (accepted && o.f_star > 0.0 && f - o.f_star <= o.rel_obj_tol * o.f_star) {
+      out.converged = true;
+      break;
+    }
+    if (!accepted) {
+      if (stage == 1) stage = 2;
+      else break;
+    }
+  }
+  if (!kkt_fresh) {
+    if (!resid_ok) nt_eval(pv, I, nw, X, s);
+    nt_gradient(pv, I, nw, X, s);
+    rows.stage = 2;
+    HIPCHK(launch_nt_measure(rows, X, nw.G, nw.part, nw.ns, s));
+    kkt = std::sqrt(nt_read(s, nw).out[0] / mn);
+    if (kkt <= o.eps_kkt) out.converged = true;
+  }
+  if (o.f_star > 0.0 && f - o.f_star <= o.rel_obj_tol * o.f_star) out.converged = true;
+  if (X != I.w64.X[0])
+    HIPCHK(hipMemcpyAsync(I.w64.X[0], X, (size_t)I.M * I.Npad * sizeof(double), hipMemcpyDeviceToDevice, s));
+  out.f = f;
+  out.kkt = kkt;
+}
+
+// copies a dense device [M][N] array into a padded device [M][Npad] one (zero pad)
+void to_padded(const Instance& I, const double* src, double* dst, hipStream_t s) {
+  const size_t Np = (size_t)I.Npad, N = (size_t)I.N;
+  HIPCHK(hipMemsetAsync(dst, 0, (size_t)I.M * Np * sizeof(double), s));
+  HIPCHK(hipMemcpy2DAsync(dst, Np * sizeof(double), src, N * sizeof(double), N * sizeof(double), (size_t)I.M,
+                          hipMemcpyDeviceToDevice, s));
+}
+
+void from_padded(const Instance& I, const double* src, double* dst, hipStream_t s) {
+  const size_t Np = (size_t)I.Npad, N = (size_t)I.N;
+  HIPCHK(hipMemcpy2DAsync(dst, N * sizeof(double), src, Np * sizeof(double), N * sizeof(double), (size_t)I.M,
+                          hipMemcpyDeviceToDevice, s));
+}
+
 }  // namespace
 
 namespace {
@@ -683,7 +943,12 @@ pdt_status pdt_make_problem(const pdt_problem_desc* descs, int64_t n_instances, 
 void pdt_destroy_problem(pdt_problem_t problem) {
   if (!problem) return;
   (void)hipStreamSynchronize(problem->stream);
-  for (Instance& I : problem->inst) drop_graphs(I);
+  for (Instance& I : problem->inst) {
+    drop_graphs(I);
+    for (hipEvent_t& e : I.nw.ev)
+      if (e) (void)hipEventDestroy(e);
+    if (I.nw.flag_h) (void)hipHostFree(I.nw.flag_h);
+  }
   if (problem->plan.graph) (void)hipGraphExecDestroy(problem->plan.graph);
   problem->plan_arena.release();
   if (problem->capture) (void)hipStreamDestroy(problem->capture);
@@ -779,6 +1044,106 @@ pdt_status pdt_objective(pdt_problem_t pb, const double* Pi, double* f_out, doub
 pdt_status pdt_kkt(pdt_problem_t pb, const double* Pi, double* kkt_out) {
   if (!kkt_out) return set_err(PDT_ERR_INVALID_ARG, "kkt_out must not be NULL");
   return objective_impl(pb, Pi, nullptr, nullptr, kkt_out);
+}
+
+pdt_status pdt_newton_solve(pdt_problem_t pb, double* Pi, const pdt_newton_opts* opts, pdt_newton_info* info) {
+  if (!pb || !Pi || !opts) return set_err(PDT_ERR_INVALID_ARG, "problem, Pi and opts must not be NULL");
+  const pdt_newton_opts o = *opts;
+  if (o.max_newton < 0) return set_err(PDT_ERR_INVALID_ARG, "max_newton must be >= 0");
+  if (!std::isfinite(o.eps_kkt) || o.eps_kkt < 0 || !std::isfinite(o.stage_switch) || o.stage_switch < 0 ||
+      !std::isfinite(o.cg_rtol) || o.cg_rtol < 0)
+    return set_err(PDT_ERR_INVALID_ARG, "eps_kkt, stage_switch and cg_rtol must be finite and >= 0");
+  if (o.cg_max < 1) return set_err(PDT_ERR_INVALID_ARG, "cg_max must be >= 1");
+  if (o.init != PDT_INIT_UNIFORM && o.init != PDT_INIT_USER)
+    return set_err(PDT_ERR_INVALID_ARG, "init must be PDT_INIT_UNIFORM or PDT_INIT_USER");
+  if (o.stage2_only != 0 && o.stage2_only != 1) return set_err(PDT_ERR_INVALID_ARG, "stage2_only must be 0 or 1");
+  if (!std::isfinite(o.f_star) || !std::isfinite(o.rel_obj_tol) || o.rel_obj_tol < 0)
+    return set_err(PDT_ERR_INVALID_ARG, "bad objective tolerance");
+  const auto t0 = std::chrono::steady_clock::now();
+  try {
+    Instance& I = pb->inst[0];
+    hipStream_t s = pb->stream;
+    ensure_work<double>(pb->arena, I, I.w64, I.P64);
+    const size_t Np = (size_t)I.Npad, N = (size_t)I.N, M = (size_t)I.M;
+    if (o.init == PDT_INIT_USER)
+      HIPCHK(launch_project_rows<double>(Pi, I.w64.X[0], (long long)M, (int)N, (int)N, (int)Np, s));
+    else
+      HIPCHK(launch_fill_rows<double>(I.w64.X[0], (long long)M, (int)N, (int)Np, 1.0 / (double)N, s));
+    NewtonRun r;
+    newton_run(pb, I, o, r);
+    from_padded(I, I.w64.X[0], Pi, s);
+    HIPCHK(hipStreamSynchronize(s));
+    if (o.history) std::memcpy(o.history, r.hist.data(), r.hist.size() * sizeof(double));
+    if (info) {
+      info->stage1_iters = r.n1;
+      info->stage2_iters = r.n2;
+      info->cg_iters = r.cg;
+      info->line_trials = r.trials;
+      info->objective = r.f;
+      info->kkt = r.kkt;
+      info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      info->converged = r.converged ? 1 : 0;
+    }
+    if (!std::isfinite(r.f)) return set_err(PDT_ERR_NUMERIC, "objective is not finite");
+    if (!r.converged) return set_err(PDT_ERR_NOT_CONVERGED, "stopped before the KKT or objective test held");
+    g_last_error.clear();
+    return PDT_OK;
+  } catch (...) {
+    return status_of_current_exception();
+  }
+}
+
+pdt_status pdt_hessian_apply(pdt_problem_t pb, const double* V, double* HV) {
+  if (!pb || !V || !HV) return set_err(PDT_ERR_INVALID_ARG, "problem, V and HV must not be NULL");
+  if (V == HV) return set_err(PDT_ERR_INVALID_ARG, "V and HV must be distinct");
+  try {
+    Instance& I = pb->inst[0];
+    hipStream_t s = pb->stream;
+    ensure_work<double>(pb->arena, I, I.w64, I.P64);
+    NewtonWork& nw = ensure_newton(pb, I);
+    const ProbView pv = view_var(I, VAR_FP64);
+    to_padded(I, V, nw.Vf, s);
+    nt_hessian(pv, I, nw, nw.Vf, nw.Gh, s);
+    from_padded(I, nw.Gh, HV, s);
+    HIPCHK(hipStreamSynchronize(s));
+    g_last_error.clear();
+    return PDT_OK;
+  } catch (...) {
+    return status_of_current_exception();
+  }
+}
+
+pdt_status pdt_newton_direction(pdt_problem_t pb, int stage, const double* Pi, double eps, double cg_rtol,
+                                int32_t cg_max, double* Dir, int32_t* row_max, int64_t* cg_iters, double* slope) {
+  if (!pb || !Pi || !Dir) return set_err(PDT_ERR_INVALID_ARG, "problem, Pi and Dir must not be NULL");
+  if (stage != 1 && stage != 2) return set_err(PDT_ERR_INVALID_ARG, "stage must be 1 or 2");
+  if (!std::isfinite(eps) || eps < 0 || !std::isfinite(cg_rtol) || cg_rtol < 0)
+    return set_err(PDT_ERR_INVALID_ARG, "eps and cg_rtol must be finite and >= 0");
+  if (cg_max < 1) return set_err(PDT_ERR_INVALID_ARG, "cg_max must be >= 1");
+  try {
+    Instance& I = pb->inst[0];
+    hipStream_t s = pb->stream;
+    ensure_work<double>(pb->arena, I, I.w64, I.P64);
+    NewtonWork& nw = ensure_newton(pb, I);
+    const ProbView pv = view_var(I, VAR_FP64);
+    double* X = I.w64.X[0];
+    to_padded(I, Pi, X, s);
+    nt_eval(pv, I, nw, X, s);
+    nt_gradient(pv, I, nw, X, s);
+    const NtRows rows{(int)I.M, (int)I.N, (int)I.Npad, stage};
+    const int it = nt_direction(pv, I, nw, rows, X, eps, cg_rtol, cg_max, s);
+    const double sl = nt_slope(I, nw, rows, X, s);
+    from_padded(I, nw.Dir, Dir, s);
+    if (row_max && stage == 2)
+      HIPCHK(hipMemcpyAsync(row_max, nw.mi, (size_t)I.M * sizeof(int), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (cg_iters) *cg_iters = it;
+    if (slope) *slope = sl;
+    g_last_error.clear();
+    return PDT_OK;
+  } catch (...) {
+    return status_of_current_exception();
+  }
 }
 
 pdt_status pdt_solve(pdt_problem_t pb, double* Pi, const pdt_solve_opts* opts, pdt_solve_info* info) {
@@ -879,6 +1244,27 @@ pdt_status pdt_replay_kernel(pdt_problem_t pb, int kernel, int precision, int64_
     }
     return PDT_OK;
   } catch (...) {
+    return status_of_current_exception();
+  }
+}
+
+pdt_status pdt_smooth_rows(const double* Pi, double* out, int64_t M, int64_t N, int32_t divisor, int64_t skip,
+                           void* stream) {
+  if (!Pi || !out) return set_err(PDT_ERR_INVALID_ARG, "Pi and out must not be NULL");
+  if (M < 1 || N < 1 || M * N > (int64_t)INT_MAX) return set_err(PDT_ERR_INVALID_ARG, "need M, N >= 1, M*N < 2^31");
+  if (divisor < 1 || skip < 0) return set_err(PDT_ERR_INVALID_ARG, "need divisor >= 1, skip >= 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Arena tmp;
+  try {
+    double* scratch = tmp.alloc<double>((size_t)smooth_scratch_doubles((long long)M, (int)N));
+    HIPCHK(launch_smooth_rows(Pi, out, (long long)M, (int)N, (int)divisor, (long long)skip, scratch, s));
+    HIPCHK(hipStreamSynchronize(s));
+    tmp.release();
+    g_last_error.clear();
+    return PDT_OK;
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    tmp.release();
     return status_of_current_exception();
   }
 }

@@ -129,6 +129,11 @@ template <typename Ts, typename Td>
 hipError_t launch_convert_pad(const Ts* src, Td* dst, long long rows, int cols, int ld_src, int ld_dst,
                               hipStream_t s);
 
+// Long-range smoothing (pdt_smooth.hip); scratch: device [smooth_scratch_doubles(M, N)]
+long long smooth_scratch_doubles(long long M, int N);
+hipError_t launch_smooth_rows(const double* Pi, double* out, long long M, int N, int divisor, long long skip,
+                              double* scratch, hipStream_t s);
+
 template <typename T>
 hipError_t launch_fill_rows(T* X, long long rows, int cols, int ld, T value, hipStream_t s);
 

@@ -1,0 +1,125 @@
+// Long-range smoothing of a POVM (Sec. 3.2, Eq. smoothing): row i >= skip becomes the
+// mean of rows i - h .. i + h, h = min(floor(i / divisor), M - 1 - i) (a window centred
+// on i that shrinks symmetrically at the top of the range); rows below skip are copied.
+//
+// Window sums are differences of column prefix sums S[i][n] = sum_{k < i} Pi[k][n],
+// carried as compensated pairs (hi, lo) (Neumaier's running sum with Knuth's TwoSum), so
+// that a difference keeps the accuracy of the window sum itself rather than of the
+// prefix sums, whose magnitude reaches the column sum (~1e4 for a million rows):
+//   1. per block of kRowsPerBlk rows, its compensated column sums;
+//   2. an exclusive compensated scan of those block sums down each column;
+//   3. the in-block prefixes, written as (S_hi, S_lo) (M + 1 rows);
+//   4. every output row from two rows of S.
+// Each pass streams the [M][N] array once (HBM-bound).  Step 4 reads only S and its own
+// entry, so the output may overwrite the input.
+#include <hip/hip_runtime.h>
+
+#include "pdt_internal.h"
+
+namespace pdt {
+
+namespace {
+
+constexpr int kRowsPerBlk = 256;
+
+// hi + lo += x, with the rounding error of the high part kept in lo
+__device__ __forceinline__ void comp_add(double& hi, double& lo, double x) {
+  const double s = hi + x;
+  const double bb = s - hi;
+  lo += (hi - (s - bb)) + (x - bb);
+  hi = s;
+}
+
+__global__ __launch_bounds__(256) void smooth_blocksum_kernel(const double* Pi, long long M, int N, long long nblk,
+                                                              double* Bh, double* Bl) {
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= nblk * N) return;
+  const long long b = t / N;
+  const int n = (int)(t % N);
+  const long long r0 = b * kRowsPerBlk;
+  const long long r1 = r0 + kRowsPerBlk < M ? r0 + kRowsPerBlk : M;
+  double hi = 0.0, lo = 0.0;
+  for (long long r = r0; r < r1; ++r) comp_add(hi, lo, Pi[r * N + n]);
+  Bh[b * N + n] = hi;
+  Bl[b * N + n] = lo;
+}
+
+__global__ __launch_bounds__(256) void smooth_scan_kernel(double* Bh, double* Bl, long long nblk, int N) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  double hi = 0.0, lo = 0.0;
+  for (long long b = 0; b < nblk; ++b) {
+    const double vh = Bh[b * N + n], vl = Bl[b * N + n];
+    Bh[b * N + n] = hi;
+    Bl[b * N + n] = lo;
+    comp_add(hi, lo, vh);
+    lo += vl;
+  }
+}
+
+__global__ __launch_bounds__(256) void smooth_prefix_kernel(const double* Pi, long long M, int N, long long nblk,
+                                                            const double* Bh, const double* Bl, double* Sh,
+                                                            double* Sl) {
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= nblk * N) return;
+  const long long b = t / N;
+  const int n = (int)(t % N);
+  const long long r0 = b * kRowsPerBlk;
+  const long long r1 = r0 + kRowsPerBlk < M ? r0 + kRowsPerBlk : M;
+  double hi = Bh[b * N + n], lo = Bl[b * N + n];
+  for (long long r = r0; r < r1; ++r) {
+    Sh[r * N + n] = hi;
+    Sl[r * N + n] = lo;
+    comp_add(hi, lo, Pi[r * N + n]);
+  }
+  if (r1 == M) {
+    Sh[M * N + n] = hi;
+    Sl[M * N + n] = lo;
+  }
+}
+
+__global__ __launch_bounds__(256) void smooth_apply_kernel(const double* Pi, const double* Sh, const double* Sl,
+                                                           long long M, int N, int divisor, long long skip,
+                                                           double* out) {
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= M * N) return;
+  const long long i = t / N;
+  const int n = (int)(t % N);
+  if (i < skip) {
+    out[t] = Pi[t];
+    return;
+  }
+  const long long hw = i / divisor;
+  const long long h = hw < M - 1 - i ? hw : M - 1 - i;
+  const long long a = (i + h + 1) * N + n, c = (i - h) * N + n;
+  const double w = (Sh[a] - Sh[c]) + (Sl[a] - Sl[c]);
+  out[t] = w / (double)(2 * h + 1);
+}
+
+unsigned grid_for(long long n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+long long smooth_scratch_doubles(long long M, int N) {
+  const long long nblk = (M + kRowsPerBlk - 1) / kRowsPerBlk;
+  return 2 * ((M + 1) * N + nblk * N);
+}
+
+hipError_t launch_smooth_rows(const double* Pi, double* out, long long M, int N, int divisor, long long skip,
+                              double* scratch, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const long long nblk = (M + kRowsPerBlk - 1) / kRowsPerBlk;
+  double* Sh = scratch;
+  double* Sl = Sh + (M + 1) * N;
+  double* Bh = Sl + (M + 1) * N;
+  double* Bl = Bh + nblk * N;
+  hipLaunchKernelGGL(smooth_blocksum_kernel, dim3(grid_for(nblk * N)), dim3(256), 0, s, Pi, M, N, nblk, Bh, Bl);
+  hipLaunchKernelGGL(smooth_scan_kernel, dim3(grid_for(N)), dim3(256), 0, s, Bh, Bl, nblk, N);
+  hipLaunchKernelGGL(smooth_prefix_kernel, dim3(grid_for(nblk * N)), dim3(256), 0, s, Pi, M, N, nblk, Bh, Bl, Sh,
+                     Sl);
+  hipLaunchKernelGGL(smooth_apply_kernel, dim3(grid_for(M * N)), dim3(256), 0, s, Pi, Sh, Sl, M, N, divisor, skip,
+                     out);
+  return hipGetLastError();
+}
+
+}  // namespace pdt

@@ -160,3 +160,25 @@ def test_stage2_only_reaches_the_same_optimum():
     assert r.stage1_iters == 0 and r.stage2_iters >= 1
     assert np.all(np.diff(r.history) <= 0)
     assert (r.f - fstar) <= 1e-7 * fstar
+
+
+def test_tangent_direction_of_the_projected_path():
+    # interior row: the derivative is d minus its mean (closed form)
+    x = np.array([0.2, 0.3, 0.5])
+    d = np.array([1.0, -2.0, 4.0])
+    assert np.allclose(newton.tangent_direction(x, d), d - d.mean(), rtol=0, atol=1e-15)
+    # hand case with zeros: support {0, 1}; zero entries with d = 3 and -5.
+    # t solves (1 - t) + (2 - t) + max(3 - t, 0) = 0  ->  t = 2, entry 2 enters with 1
+    x = np.array([0.6, 0.4, 0.0, 0.0])
+    d = np.array([1.0, 2.0, 3.0, -5.0])
+    assert np.allclose(newton.tangent_direction(x, d), [-1.0, 0.0, 1.0, 0.0], rtol=0, atol=1e-15)
+    # random rows with exact zeros against a small-step difference of the projection
+    rng = np.random.default_rng(7)
+    for _ in range(50):
+        x = simplex.project_rows(rng.normal(size=(1, 12)) * 2.0)[0]
+        d = rng.normal(size=12)
+        v = newton.tangent_direction(x, d)
+        a = 1e-7
+        fd = (simplex.project_rows((x + a * d)[None, :])[0] - x) / a
+        assert np.max(np.abs(v - fd)) <= 1e-6 * max(1.0, np.max(np.abs(v)))
+        assert abs(v.sum()) <= 1e-13 and np.all(v[x == 0.0] >= 0.0)

@@ -101,6 +101,9 @@ def main():
                          "fixed iterations; c4: 256-detector batch")
     ap.add_argument("--kernels-only", action="store_true",
                     help="short run for profilers: 200 iterations, then 200 launches of each kernel")
+    ap.add_argument("--no-newton", action="store_true", help="skip the Newton-CG legs")
+    ap.add_argument("--newton-only", action="store_true",
+                    help="short run for profilers: 100 two-stage Newton-CG steps on the default workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver is a single-GPU kernel path",
@@ -135,6 +138,15 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("[bench] kernels-only pass done")
+        return
+
+    if args.newton_only:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = pb.newton(Pi, max_newton=100, eps_kkt=0.0)
+        torch.cuda.synchronize()
+        log(f"[bench] newton-only pass: {info['stage1_iters']}+{info['stage2_iters']} steps, cg {info['cg_iters']}, "
+            f"trials {info['line_trials']}, {time.perf_counter() - t:.3f} s")
         return
 
     # reference optimum: a long FP64 solve with the scaled step, certified by its KKT residual
@@ -177,6 +189,33 @@ def main():
     for r in mixed:
         log(f"[bench] mixed solve: iters={r['iters']} (fp64 refinement {r['refine_iters']}) wall={r['wall']:.3f}s "
             f"converged={r['converged']} relobj={(r['objective'] - f_ref) / f_ref:.2e}")
+
+    # the paper's own solver (App. B, Algorithms 1-3): two-stage Newton-CG on the same band
+    # kernels with the paper's parameters, from the same start and against the same
+    # reference; a fixed budget of Newton steps (it does not reach 1e-9 on this problem)
+    def newton(stage2_only=False, steps=600):
+        hist = np.zeros(steps + 1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = pb.newton(Pi, max_newton=steps, eps_kkt=1e-13, f_star=f_ref, rel_obj_tol=args.tol,
+                         stage2_only=stage2_only, history=hist)
+        torch.cuda.synchronize()
+        info["wall"] = time.perf_counter() - t
+        n = 1 + info["stage1_iters"] + info["stage2_iters"]
+        rel = (hist[:n] - f_ref) / f_ref
+        info["steps_to"] = {f"{tol:g}": (int(np.argmax(rel <= tol)) if (rel <= tol).any() else None)
+                            for tol in (1e-1, 1e-2, 1e-3, 1e-4, 1e-6)}
+        info["relobj"] = float(rel[-1])
+        log(f"[bench] newton{' (stage 2 only)' if stage2_only else ''}: stage1={info['stage1_iters']} "
+            f"stage2={info['stage2_iters']} cg={info['cg_iters']} trials={info['line_trials']} "
+            f"wall={info['wall']:.3f}s converged={info['converged']} relobj={info['relobj']:.2e} "
+            f"kkt={info['kkt']:.2e} steps_to={info['steps_to']}")
+        return info
+
+    nt = nt_s2 = None
+    if not args.no_newton:
+        nt = newton()
+        nt_s2 = newton(stage2_only=True)
 
     # dominant kernel: the transposed band product + projected step, timed on the stream
     # it is launched on
@@ -242,6 +281,13 @@ def main():
                                            np.median([r["wall"] for r in mixed]))},
         "fp32": {"time_s": fp32["wall"], "iters": fp32["iters"], "tol": 1e-4, "max_iters": 20000,
                  "converged": fp32["converged"], "relobj": (fp32["objective"] - f_ref) / f_ref},
+        "newton": None if nt is None else {"steps": 600, "time_s": nt["wall"], "stage1_iters": int(nt["stage1_iters"]),
+                   "stage2_iters": int(nt["stage2_iters"]), "cg_iters": int(nt["cg_iters"]),
+                   "line_trials": int(nt["line_trials"]), "converged": int(nt["converged"]), "tol": args.tol,
+                   "relobj": nt["relobj"], "kkt": float(nt["kkt"]), "steps_to": nt["steps_to"],
+                   "ms_per_cg_iteration": nt["wall"] / max(1, nt["cg_iters"]) * 1e3,
+                   "stage2_only": {"time_s": nt_s2["wall"], "stage2_iters": int(nt_s2["stage2_iters"]),
+                                   "relobj": nt_s2["relobj"], "steps_to": nt_s2["steps_to"]}},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -56,6 +56,8 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=150)
     ap.add_argument("--K", type=int, default=30000)
     ap.add_argument("--hidden", type=int, default=512)
+    ap.add_argument("--uniform-tests", type=int, default=4,
+                    help="test detectors that also run the uniform-step solve (it does not reach 1e-8 in K)")
     ap.add_argument("--out", default="")
     args = ap.parse_args(argv)
 
@@ -91,16 +93,18 @@ def main(argv=None):
     log(f"[ws] trained {model.num_params} parameters in {t_train:.1f} s, loss {hist[0]:.3e} -> {hist[-1]:.3e}")
 
     results = []
-    for inst in test:
+    for ti, inst in enumerate(test):
         pb = _pdt.Problem.from_instance(inst)
         runs = {}
         DIAG, UNIFORM = _pdt.PDT_STEP_DIAG, _pdt.PDT_STEP_UNIFORM
         # the scaled step's Lipschitz constant is set up once per problem, outside the timings
         pb.solve(torch.zeros((inst.M, inst.N), dtype=torch.float64, device="cuda"), max_iters=0, scaling=DIAG)
-        for name, init, prec, sc in (("cold_fp64", _pdt.PDT_INIT_UNIFORM, _pdt.PDT_FP64, DIAG),
-                                     ("warm_fp64", _pdt.PDT_INIT_LEARNED, _pdt.PDT_FP64, DIAG),
-                                     ("warm_mixed", _pdt.PDT_INIT_LEARNED, _pdt.PDT_MIXED, DIAG),
-                                     ("cold_fp64_uniform", _pdt.PDT_INIT_UNIFORM, _pdt.PDT_FP64, UNIFORM)):
+        plan = [("cold_fp64", _pdt.PDT_INIT_UNIFORM, _pdt.PDT_FP64, DIAG),
+                ("warm_fp64", _pdt.PDT_INIT_LEARNED, _pdt.PDT_FP64, DIAG),
+                ("warm_mixed", _pdt.PDT_INIT_LEARNED, _pdt.PDT_MIXED, DIAG)]
+        if ti < args.uniform_tests:
+            plan.append(("cold_fp64_uniform", _pdt.PDT_INIT_UNIFORM, _pdt.PDT_FP64, UNIFORM))
+        for name, init, prec, sc in plan:
             Pi = torch.zeros((inst.M, inst.N), dtype=torch.float64, device="cuda")
             h = torch.zeros(args.K, dtype=torch.float64, device="cuda")
             torch.cuda.synchronize()
@@ -141,9 +145,19 @@ def main(argv=None):
         pb.close()
 
     def med(key, tol):
-        vals = [r[key][f"time_{tol:g}"] for r in results]
+        vals = [r[key][f"time_{tol:g}"] for r in results if key in r]
         vals = [v for v in vals if v is not None]
         return float(np.median(vals)) if vals else None
+
+    def stats(vals, seed=0):
+        """median, interquartile range and a 95% bootstrap interval of the median"""
+        v = np.asarray(vals, dtype=np.float64)
+        if v.size == 0:
+            return None
+        rng = np.random.default_rng(seed)
+        boots = np.median(rng.choice(v, size=(2000, v.size), replace=True), axis=1)
+        return {"n": int(v.size), "median": float(np.median(v)), "iqr": [float(np.percentile(v, 25)), float(np.percentile(v, 75))],
+                "ci95_median": [float(np.percentile(boots, 2.5)), float(np.percentile(boots, 97.5))]}
 
     summary = {"family": f"M={M_FAMILY} N={N_PAD} D=19661", "train_detectors": args.train,
                "train_columns": int(sum(p.X.shape[0] for p in pairs)), "target_iters": args.target_iters,
@@ -153,9 +167,18 @@ def main(argv=None):
         summary[f"median_time_{tol:g}"] = {k: med(k, tol) for k in ("cold_fp64", "warm_fp64", "warm_mixed",
                                                                     "cold_fp64_uniform")}
         summary[f"median_iters_{tol:g}"] = {
-            k: (float(np.median([r[k][f"iters_{tol:g}"] for r in results if r[k][f"iters_{tol:g}"] is not None]))
-                if any(r[k][f"iters_{tol:g}"] is not None for r in results) else None)
+            k: (float(np.median([r[k][f"iters_{tol:g}"] for r in results
+                                 if k in r and r[k][f"iters_{tol:g}"] is not None]))
+                if any(k in r and r[k][f"iters_{tol:g}"] is not None for r in results) else None)
             for k in ("cold_fp64", "warm_fp64", "warm_mixed", "cold_fp64_uniform")}
+    for tol in (1e-6, 1e-8):
+        key = f"{tol:g}"
+        summary[f"stats_time_{key}"] = {k: stats([r[k][f"time_{key}"] for r in results if k in r and r[k][f"time_{key}"] is not None])
+                                        for k in ("cold_fp64", "warm_fp64", "warm_mixed")}
+        paired = [(r["cold_fp64"][f"iters_{key}"], r["warm_fp64"][f"iters_{key}"]) for r in results]
+        summary[f"reached_{key}"] = {k: int(sum(1 for r in results if k in r and r[k][f"iters_{key}"] is not None))
+                                     for k in ("cold_fp64", "warm_fp64", "warm_mixed", "cold_fp64_uniform")}
+        summary[f"stats_iter_ratio_cold_over_warm_{key}"] = stats([c / w for c, w in paired if c and w])
     log(json.dumps({k: v for k, v in summary.items() if k != "tests"}, indent=1))
     if args.out:
         with open(args.out, "w") as fh:

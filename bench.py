@@ -96,9 +96,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-9)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "loop"],
                     help="c2: M=4096 N=65 D=5000 to tolerance (default); c3: M=1e6 N=100 D=1e5, "
-                         "fixed iterations; c4: 256-detector batch")
+                         "fixed iterations; c4: 256-detector batch; loop: the paper's experiment in synthetic "
+                         "form (M=1,210,581 N=151 D=1076), fixed iterations")
     ap.add_argument("--kernels-only", action="store_true",
                     help="short run for profilers: 200 iterations, then 200 launches of each kernel")
     ap.add_argument("--no-newton", action="store_true", help="skip the Newton-CG legs")
@@ -116,8 +117,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "c4":
         return bench_batch(args)
-    if args.workload == "c3":
-        return bench_mega(args)
+    if args.workload in ("c3", "loop"):
+        return bench_mega(args, workload=args.workload)
     inst = synth.c2_medium()
     M, N, D = inst.M, inst.N, inst.D
     log(f"[bench] workload {inst.name}: M={M} N={N} D={D}")
@@ -355,14 +356,22 @@ def replay_time(pb, kern, prec, reps):
     return e0.elapsed_time(e1) / reps * 1e-3
 
 
-def bench_mega(args, iters=64):
-    """M=1e6, N=100, D=1e5 (99-bin detector with 1% crosstalk, mu on [0, 1.1e6], 1e8 shots,
-    gamma 1e-5): a fixed number of FP64 and mixed-precision iterations with the row-scaled
-    step from Pi = 1/N, and the per-launch times of the band kernels at this size."""
+def bench_mega(args, iters=64, workload="c3"):
+    """A fixed number of FP64 and mixed-precision iterations with the row-scaled step from
+    Pi = 1/N, and the per-launch times of the band kernels, on one of the two largest
+    workloads:
+      c3:   M=1e6, N=100, D=1e5 (99-bin detector with 1% crosstalk, mu on [0, 1.1e6], 1e8
+            shots, gamma 1e-5; band of 9.3e8 entries);
+      loop: the paper's experiment in synthetic form, M=1,210,581, N=151, D=1076 with
+            mu_d = d^2, 5e5 trials per probe, gamma 1e-5 (band of 8.9e6 entries: the
+            transposed product streams the [M][Npad] iterates, so its roofline is HBM)."""
     import torch
     from paper_2404_02844_amd import _pdt, synth
     t0 = time.perf_counter()
-    inst = synth.c3_mega(workers=min(16, os.cpu_count() or 1))
+    if workload == "loop":
+        inst = synth.loop_paper_scale(workers=min(16, os.cpu_count() or 1))
+    else:
+        inst = synth.c3_mega(workers=min(16, os.cpu_count() or 1))
     log(f"[bench] generated {inst.name} in {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
     pb = _pdt.Problem.from_instance(inst)
@@ -391,21 +400,36 @@ def bench_mega(args, iters=64):
     log("[bench] kernel times (ms): " + " ".join(f"{k}={v * 1e3:.3f}" for k, v in times.items()))
     flops = 2.0 * nnz * N
     achieved = flops / times["ftr"] / 1e12
+    if workload == "loop":
+        # algorithmic bytes of the transposed product: X_k and X_k-1 read, X_k+1 written
+        # ([M][Npad] FP64 each), R read ([D][Npad]), one anchor per (row tile, probe) pair
+        npad = (N + 15) // 16 * 16
+        tb = (3.0 * M * npad + inst.D * npad) * 8.0
+        gbs = tb / times["ftr"] / 1e9
+        roof = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
+                "traffic": None, "kernel": "ftr_kernel<double> (F^T R band product + projected step)",
+                "per_launch_bytes": tb, "mfma_tflops": achieved, "avg_launch_s": times["ftr"],
+                "fx_avg_launch_s": times["fx"], "iteration_s": times["iteration"],
+                "mixed_ftr_s": times["mixed_ftr"], "mixed_fx_s": times["mixed_fx"],
+                "mixed_iteration_s": times["mixed_iteration"]}
+    else:
+        roof = None
     out = {
         "metric": METRIC, "value": res["fp64"]["elem_iters_per_s"], "unit": "POVM-elem*iters/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["fp64"]["s_per_solve"] * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": inst.name, "M": M, "N": N, "D": inst.D, "gamma": inst.gamma,
-                   "pmf_threshold": inst.threshold, "tail": "lump", "iters": iters, "band_entries": nnz,
+                   "pmf_threshold": inst.threshold, "tail": "truncate" if workload == "loop" else "lump",
+                   "iters": iters, "band_entries": nnz,
                    "step": "row-scaled (Hessian diagonal)"},
         "mixed": res["mixed"],
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "ftr_kernel<double> (F^T R band product + projected step)",
-                     "per_launch_flops": flops, "avg_launch_s": times["ftr"], "fx_avg_launch_s": times["fx"],
-                     "iteration_s": times["iteration"],
-                     "mixed_ftr_tflops": flops / times["mixed_ftr"] / 1e12,
-                     "mixed_fx_tflops": flops / times["mixed_fx"] / 1e12},
+        "roofline": roof or {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                             "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                             "kernel": "ftr_kernel<double> (F^T R band product + projected step)",
+                             "per_launch_flops": flops, "avg_launch_s": times["ftr"], "fx_avg_launch_s": times["fx"],
+                             "iteration_s": times["iteration"],
+                             "mixed_ftr_tflops": flops / times["mixed_ftr"] / 1e12,
+                             "mixed_fx_tflops": flops / times["mixed_fx"] / 1e12},
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)

@@ -10,6 +10,8 @@
    its objective.
 3. The momentum method (row-scaled step) on the same problem, to the same tolerance,
    for reference.
+4. (--sweep) The stage-switch threshold and the CG budget per Newton step, varied
+   around the paper's values (|phi'(0)| <= 1e-4, 50 iterations), 800 steps each.
 
 Every solve runs in the HIP library; this module only sequences calls and scores.
 
@@ -105,11 +107,37 @@ def run(inst, dev, max_newton: int, eps_kkt: float, log) -> dict:
     return res
 
 
+def sweep(inst, dev, log) -> list:
+    import torch
+    pb = _pdt.Problem.from_instance(inst)
+    Pi = torch.empty((inst.M, inst.N), dtype=torch.float64, device=dev)
+    f_ref = pb.solve(Pi, max_iters=30000, scaling=_pdt.PDT_STEP_DIAG)["objective"]
+    out = []
+    for switch in (1e-4, 1e-6, 1e-8, 0.0):
+        for cg_max in (50, 20):
+            hist = np.zeros(801)
+            t = time.perf_counter()
+            r = pb.newton(Pi, max_newton=800, eps_kkt=0.0, stage_switch=switch, cg_max=cg_max, history=hist)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            n = 1 + r["stage1_iters"] + r["stage2_iters"]
+            rec = {"stage_switch": switch, "cg_max": cg_max, "time_s": el, "stage1": r["stage1_iters"],
+                   "stage2": r["stage2_iters"], "cg": r["cg_iters"], "trials": r["line_trials"],
+                   "relobj": (r["objective"] - f_ref) / f_ref, "kkt": r["kkt"],
+                   "steps_to": rel_steps(hist[:n], f_ref, (1e-1, 1e-2, 1e-3, 1e-4, 1e-6))}
+            log(f"[sweep] switch {switch:g} cg {cg_max}: {rec['stage1']}+{rec['stage2']} steps {el:.2f} s "
+                f"relobj {rec['relobj']:.2e} kkt {rec['kkt']:.2e} steps_to {rec['steps_to']}")
+            out.append(rec)
+    pb.close()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--max-newton", type=int, default=400)
     ap.add_argument("--eps-kkt", type=float, default=1e-12)
     ap.add_argument("--out", default="")
+    ap.add_argument("--sweep", action="store_true", help="only the stage-switch / CG-budget sweep")
     args = ap.parse_args(argv)
     import torch
     dev = torch.device("cuda:0")
@@ -117,6 +145,12 @@ def main(argv=None):
     def log(*a):
         print(*a, flush=True)
 
+    if args.sweep:
+        out = sweep(synth.c2_medium(), dev, log)
+        if args.out:
+            with open(args.out, "w") as fh:
+                json.dump(out, fh)
+        return out
     out = []
     for seed_off, gamma in ((0, 0.0), (0, 1e-4)):
         base = synth.c2_medium(seed_offset=seed_off)

@@ -111,6 +111,61 @@ def click_detector_povm(M: int, B: int, eta: float, dark: float = 0.0,
     return out
 
 
+LOOP_R, LOOP_ETA_LOOP, LOOP_ETA_DET = 0.91644, 0.90524, 0.528  # the paper's fitted device (Sec. 4.1)
+
+
+def loop_bin_probs(J: int, R: float, eta_loop: float, eta_det: float) -> np.ndarray:
+    """Per-photon click probability of time bins 1..J of the beam-splitter loop detector
+    (the single-photon factors of Eq. pj_fock): R eta_det for the first bin, then
+    (1 - R)^2 / R (R eta_loop)^(j-1) eta_det."""
+    j = np.arange(1, J + 1, dtype=np.float64)
+    q = (1.0 - R) ** 2 / R * (R * eta_loop) ** (j - 1.0) * eta_det
+    q[0] = R * eta_det
+    return q
+
+
+_POOL_Q = None
+
+
+def _loop_rows(args):
+    i0, i1 = args
+    q = _POOL_Q
+    J = q.shape[0]
+    i = np.arange(i0, i1, dtype=np.float64)[:, None]
+    p = -np.expm1(i * np.log1p(-q)[None, :])  # p_j(i) = 1 - (1 - q_j)^i (Eq. pj_fock)
+    dist = np.zeros((i1 - i0, J + 1))
+    dist[:, 0] = 1.0
+    for j in range(J):  # clicked-bin count, one independent bin at a time
+        pj = p[:, j:j + 1]
+        dist[:, 1:j + 2] = dist[:, 1:j + 2] * (1.0 - pj) + dist[:, 0:j + 1] * pj
+        dist[:, 0] *= 1.0 - p[:, j]
+    return dist
+
+
+def loop_detector_povm(M: int, J: int = 150, R: float = LOOP_R, eta_loop: float = LOOP_ETA_LOOP,
+                       eta_det: float = LOOP_ETA_DET, workers: int = 1, block: int = 4096) -> np.ndarray:
+    """Pi_true[i, n] = P(n of the J time bins click | i photons) for the time-multiplexed
+    loop detector of Sec. 4.1: bins click independently with p_j(i) = 1 - (1 - q_j)^i
+    (Eq. pj_fock), so the count is Poisson-binomial; it is built by the exact one-bin-
+    at-a-time recursion (data generation only).  Outcomes n = 0..J (N = J + 1)."""
+    global _POOL_Q
+    _POOL_Q = loop_bin_probs(J, R, eta_loop, eta_det)
+    try:
+        spans = [(i0, min(M, i0 + block)) for i0 in range(0, M, block)]
+        if workers <= 1:
+            parts = [_loop_rows(sp) for sp in spans]
+        else:
+            import multiprocessing as mp
+            with mp.get_context("fork").Pool(workers) as pool:
+                parts = pool.map(_loop_rows, spans)
+    finally:
+        _POOL_Q = None
+    out = np.concatenate(parts, axis=0)
+    out = np.clip(out, 0.0, None)
+    out /= out.sum(axis=1, keepdims=True)
+    return out
+
+
 def _probe_window(mu: float, lo_cap: int, hi_cap: int) -> tuple[int, int]:
     s = math.sqrt(max(mu, 1.0))
     lo = max(0, int(math.floor(mu - 12.0 * s - 40)))
@@ -250,6 +305,23 @@ def c3_mega(M: int = 1_000_000, D: int = 100_000, workers: int = 16) -> Instance
     return make_instance(f"c3_m{M}_n100_d{D}", M=M, B=99, eta=0.8, crosstalk=0.01, D=D,
                          mu_max=1.1 * M, shots=1e8, gamma=1e-5, tail_mode=LUMP, threshold=1e-16,
                          rng=rng_for(3), seed=SEED_BASE + 3, workers=workers)
+
+
+def loop_paper_scale(M: int = 1_210_581, D: int = 1076, J: int = 150, shots: float = 5e5, gamma: float = 1e-5,
+                     workers: int = 16, seed_offset: int = 0) -> Instance:
+    """The paper's experiment in synthetic form (Sec. 2.1, Sec. 4.1): the beam-splitter
+    loop detector with its fitted R, eta_loop, eta_det, 150 time bins (N = 151), D = 1076
+    coherent probes with mu_d = d^2, M = 1,210,581, 5e5 trials per probe, band tau = 1e-16
+    (the probes' bands end below M - 1, so F is taken as printed, without a lumped tail)."""
+    mu = np.arange(D, dtype=np.float64) ** 2
+    ext = int(math.ceil(mu[-1] + 14.0 * math.sqrt(max(mu[-1], 1.0)) + 60))
+    Pi_ext = loop_detector_povm(max(M, ext + 1), J, workers=workers)
+    q = outcome_probs(mu, Pi_ext, M, TRUNCATE)
+    P = sample_outcomes(q, shots, rng_for(6 + seed_offset))
+    return Instance(name=f"loop_m{M}_n{J + 1}_d{D}", M=M, N=J + 1, D=D, mu=mu, P=np.ascontiguousarray(P),
+                    Pi_true=np.ascontiguousarray(Pi_ext[:M]), gamma=gamma, tail_mode=TRUNCATE, threshold=1e-16,
+                    shots=shots, seed=SEED_BASE + 6 + seed_offset,
+                    detector=dict(kind="loop", J=J, R=LOOP_R, eta_loop=LOOP_ETA_LOOP, eta_det=LOOP_ETA_DET))
 
 
 def random_detector(rng: np.random.Generator, M: int, *, bins=(8, 128), eta=(0.5, 0.95),

@@ -105,6 +105,10 @@ def lib() -> ctypes.CDLL:
         L.pdt_problem_set_tiles.argtypes = [vp, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.pdt_problem_tiles.argtypes = [vp, i64, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         L.pdt_replay_kernel.argtypes = [vp, ctypes.c_int, ctypes.c_int, i64]
+        L.pdt_problem_set_fx_split.argtypes = [vp, i64, ctypes.c_int]
+        L.pdt_problem_fx_split.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_int)]
+        L.pdt_problem_set_fx_split.restype = ctypes.c_int
+        L.pdt_problem_fx_split.restype = ctypes.c_int
         L.pdt_replay_kernel.restype = ctypes.c_int
         L.pdt_model_create.argtypes = [i64, i64, i64, vp, vp, ctypes.POINTER(vp)]
         L.pdt_model_destroy.argtypes = [vp]
@@ -362,6 +366,14 @@ class Problem:
 
     def tiles(self, precision):
         return pdt_problem_tiles(self.handle, 0, precision)
+
+    def set_fx_split(self, split):
+        _check(lib().pdt_problem_set_fx_split(self.handle, 0, int(split)))
+
+    def fx_split(self):
+        v = ctypes.c_int()
+        _check(lib().pdt_problem_fx_split(self.handle, 0, ctypes.byref(v)))
+        return v.value
 
     def close(self):
         if self.handle:

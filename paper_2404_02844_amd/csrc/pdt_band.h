@@ -98,10 +98,19 @@ __device__ __forceinline__ void reduce_tiles(const AccT (&acc)[NT], double* S, i
 
 // TS: storage type of X, O, R, P.  TC: MFMA operand type (TS, or float under TS = double
 // for the mixed path, whose forward product works on X_new - X_cur: FX_DELTA).
+//
+// Split contraction (pv.fx_split = S > 1, for problems with few probe tiles and long
+// photon-number ranges): workgroup wg takes part wg % S of tile wg / S's chunks, writes
+// its partial tile and its regulariser partial, and the last of the S workgroups to
+// finish (a per-tile counter) sums the S partial tiles in workgroup order and runs the
+// epilogue.  Partials: [wg] regulariser shares, then [nwg + tile] residual sums.
 template <typename TS, typename TC, int NT, int KS>
-__device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode, int tile,
-                                        int ntiles) {
+__device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode, int wg,
+                                        int nwg) {
   if ((mode == FX_ITER || mode == FX_DELTA || mode == FX_EVAL_PREV || mode == FX_RESYNC) && st->done) return;
+  const int nsplit = pv.fx_split;
+  const int tile = wg / nsplit;
+  const int sidx = wg - tile * nsplit;
   typedef TS T;
   typedef typename Acc<TC>::type AccT;
   const bool iter = mode == FX_ITER || mode == FX_DELTA;
@@ -157,8 +166,9 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
     r = pv.r4[mrow];
   };
   const int nch = mhi >= mlo ? (mhi - mlo) / kChunkM + 1 : 0;
-  const int c0 = (nch * wv) / KS;
-  const int c1 = (nch * (wv + 1)) / KS;
+  const int cs0 = (nch * sidx) / nsplit, cs1 = (nch * (sidx + 1)) / nsplit;
+  const int c0 = cs0 + ((cs1 - cs0) * wv) / KS;
+  const int c1 = cs0 + ((cs1 - cs0) * (wv + 1)) / KS;
   const double mu4 = (mu * mu) * (mu * mu);
   // Anchor of the first chunk whose photon numbers come within reach of this lane's band
   // (ma + 60 >= lo_d, ma <= hi_d) and whose value does not underflow (dense rows of bright
@@ -193,9 +203,9 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
   double reg = 0.0;
   if (pv.gamma != 0.0 && M > 1) {
     const long long pairs = (long long)(M - 1);
-    const long long W = ntiles;
+    const long long W = nwg;
     const long long per = (pairs + W - 1) / W;
-    const long long r0 = (long long)tile * per;
+    const long long r0 = (long long)wg * per;
     const long long r1 = r0 + per < pairs ? r0 + per : pairs;
     const long long cnt = (r1 > r0 ? r1 - r0 : 0) * (long long)N;
     for (long long q = tid; q < cnt; q += 64 * KS) {
@@ -250,6 +260,37 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
   }
   reduce_tiles<TC, NT, KS>(acc, S, LDT, wv, i, kq);
 
+  if (nsplit > 1) {
+    constexpr int kTile = 16 * 16 * NT;
+    double* mine = b.fx_part + (size_t)wg * kTile;
+    for (int q = tid; q < kTile; q += 64 * KS) mine[q] = S[(q / (16 * NT)) * LDT + q % (16 * NT)];
+    double rp = (pv.gamma != 0.0 && M > 1) ? pv.gamma * reg : 0.0;
+    rp = group_sum<64>(rp);
+    if (lane == 0) red[wv] = rp;
+    __threadfence();  // this thread's share of the partial tile, visible device-wide
+    __syncthreads();
+    __shared__ int is_last;
+    if (tid == 0) {
+      double sr = 0.0;
+#pragma unroll
+      for (int w = 0; w < KS; ++w) sr += red[w];
+      b.partials[wg] = sr;
+      const unsigned prev = atomicAdd(&b.fx_count[tile], 1u);
+      is_last = prev == (unsigned)(nsplit - 1);
+      if (is_last) b.fx_count[tile] = 0u;  // ready for the next launch
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();  // the other workgroups' partial tiles are visible from here on
+    const double* parts = b.fx_part + (size_t)tile * nsplit * kTile;
+    for (int q = tid; q < kTile; q += 64 * KS) {
+      double v = 0.0;
+      for (int sp = 0; sp < nsplit; ++sp) v += __builtin_nontemporal_load(parts + (size_t)sp * kTile + q);
+      S[(q / (16 * NT)) * LDT + q % (16 * NT)] = v;
+    }
+    __syncthreads();
+  }
+
   // epilogue: wave wv finishes probe rows 4 wv + kq
   T beta_acc = 0;
   if (iter) {
@@ -294,8 +335,9 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
     }
   }
 
-  // the regulariser partial formed before the main loop
-  if (pv.gamma != 0.0 && M > 1) part += pv.gamma * reg;
+  // the regulariser partial formed before the main loop (split: already written per
+  // workgroup)
+  if (nsplit == 1 && pv.gamma != 0.0 && M > 1) part += pv.gamma * reg;
   part = group_sum<64>(part);
   if (lane == 0) red[wv] = part;
   __syncthreads();
@@ -303,7 +345,7 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < KS; ++w) s += red[w];
-    b.partials[tile] = s;
+    b.partials[nsplit == 1 ? tile : nwg + tile] = s;
   }
 }
 
@@ -587,7 +629,8 @@ __global__ __launch_bounds__(64 * KS) void ftr_batch_kernel(const BatchInst<TS>*
 // ---------------------------------------------------------------------------------------
 template <typename TS, typename TC, int NT, int KS>
 static void fx_go(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode, hipStream_t s) {
-  hipLaunchKernelGGL((fx_kernel<TS, TC, NT, KS>), dim3(fx_num_waves(pv)), dim3(64 * KS), 0, s, pv, b, st, mode);
+  hipLaunchKernelGGL((fx_kernel<TS, TC, NT, KS>), dim3(fx_num_tiles(pv) * pv.fx_split), dim3(64 * KS), 0, s, pv, b,
+                     st, mode);
 }
 template <typename TS, typename TC, int NT, int KS>
 static void ftr_go(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode, double step,

@@ -145,6 +145,12 @@ struct Instance {
   const double* graph_w[3] = {nullptr, nullptr, nullptr};
   // waves per workgroup forced per variant and kernel (0: from the tuning table)
   int ks_force[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  // split contraction of the forward product: workgroups per 16-probe tile
+  int fx_split = 1;
+  int fx_split_auto = 1;
+  size_t fx_part_cap = 0;        // doubles allocated for fx_part
+  double* fx_part = nullptr;
+  unsigned* fx_count = nullptr;
   NewtonWork nw;
 };
 
@@ -222,6 +228,7 @@ ProbView view_of(const Instance& I) {
   pv.Npad = (int)I.Npad;
   pv.lump = I.lump;
   pv.gamma = I.gamma;
+  pv.fx_split = I.fx_split;
   return pv;
 }
 
@@ -246,6 +253,8 @@ Bufs<T> bufs_of(const Instance& I, const Work<T>& w, double* history, const doub
     b.X[k] = w.X[k];
     b.O[k] = w.O[k];
   }
+  b.fx_part = I.fx_part;
+  b.fx_count = I.fx_count;
   b.P = w.P;
   b.R_acc = w.R_acc;
   b.R_rej = w.R_rej;
@@ -297,6 +306,20 @@ void validate_desc(const pdt_problem_desc& d) {
     for (int64_t k = 0; k < n; ++k)
       if (!std::isfinite(d.P[k]) || d.P[k] < 0) throw ArgError{"P must be finite and >= 0"};
   }
+}
+
+constexpr int kMaxFxSplit = 16;
+
+// Workgroups per 16-probe tile of the forward product; grows the partial-tile scratch
+// when needed (allocations stay with the problem).
+void set_fx_split(Arena& A, Instance& I, int split) {
+  const size_t n_dt = (size_t)((I.D + 15) / 16);
+  const size_t need = split > 1 ? n_dt * (size_t)split * 16 * (size_t)I.Npad : 0;
+  if (need > I.fx_part_cap) {
+    I.fx_part = A.alloc<double>(need);
+    I.fx_part_cap = need;
+  }
+  I.fx_split = split;
 }
 
 // Power iteration for lambda_max(W^(1/2) (2 F^T F + 2 gamma L) W^(1/2)) with the band
@@ -433,7 +456,19 @@ void setup_instance(pdt_problem_s* pb, Instance& I, const pdt_problem_desc& d) {
   HIPCHK(hipMemcpyAsync(I.mt_aoff, aoff.data(), (n_mt + 1) * sizeof(long long), hipMemcpyHostToDevice, s));
   HIPCHK(launch_setup_anchors(view_of(I), I.mt_aoff, I.anchors, s));
 
-  I.n_partials = (int)std::max(n_dt, n_mt);
+  // Forward products of problems with few probe tiles and long photon-number ranges
+  // split each tile's contraction over up to 8 workgroups (about two workgroups per CU
+  // in all, at least 32 64-entry chunks per workgroup).
+  int maxch = 0;
+  for (size_t t = 0; t < n_dt; ++t)
+    if (dt_mhi[t] >= dt_mlo[t]) maxch = std::max(maxch, (dt_mhi[t] - dt_mlo[t]) / kChunkM + 1);
+  I.fx_split_auto = 1;
+  if (n_dt < 256) I.fx_split_auto = std::max(1, std::min({8, (int)((512 + n_dt - 1) / n_dt), maxch / 32}));
+  I.fx_count = A.alloc<unsigned>(n_dt);
+  HIPCHK(hipMemsetAsync(I.fx_count, 0, n_dt * sizeof(unsigned), s));
+  set_fx_split(A, I, I.fx_split_auto);
+  // room for the partials of any split up to kMaxFxSplit
+  I.n_partials = (int)std::max(n_dt * (kMaxFxSplit + 1), n_mt);
   I.partials = A.alloc<double>(I.n_partials);
   I.st = A.alloc<SolverState>(1);
   I.st_eval = A.alloc<SolverState>(1);
@@ -700,6 +735,8 @@ Bufs<double> nt_bufs(const Instance& I, const NewtonWork& nw, const double* X, d
   b.partials = nw.bpart;
   b.n_partials = I.n_partials;
   b.history = nullptr;
+  b.fx_part = I.fx_part;
+  b.fx_count = I.fx_count;
   return b;
 }
 
@@ -988,6 +1025,28 @@ pdt_status pdt_problem_set_tiles(pdt_problem_t pb, int64_t instance, int precisi
   } catch (...) {
     return status_of_current_exception();
   }
+}
+
+pdt_status pdt_problem_set_fx_split(pdt_problem_t pb, int64_t instance, int split) {
+  if (!pb) return set_err(PDT_ERR_INVALID_ARG, "problem is NULL");
+  if (instance < 0 || instance >= (int64_t)pb->inst.size()) return set_err(PDT_ERR_INVALID_ARG, "bad instance");
+  if (split < 0 || split > kMaxFxSplit) return set_err(PDT_ERR_INVALID_ARG, "split must be in [0, 16]");
+  try {
+    Instance& I = pb->inst[(size_t)instance];
+    HIPCHK(hipStreamSynchronize(pb->stream));
+    drop_graphs(I);  // captured launches carry the old grid
+    set_fx_split(pb->arena, I, split == 0 ? I.fx_split_auto : split);
+    return PDT_OK;
+  } catch (...) {
+    return status_of_current_exception();
+  }
+}
+
+pdt_status pdt_problem_fx_split(pdt_problem_t pb, int64_t instance, int* split) {
+  if (!pb || !split) return set_err(PDT_ERR_INVALID_ARG, "problem and split must not be NULL");
+  if (instance < 0 || instance >= (int64_t)pb->inst.size()) return set_err(PDT_ERR_INVALID_ARG, "bad instance");
+  *split = pb->inst[(size_t)instance].fx_split;
+  return PDT_OK;
 }
 
 pdt_status pdt_problem_tiles(pdt_problem_t pb, int64_t instance, int precision, int* ks_fx, int* ks_ftr) {
@@ -1607,10 +1666,13 @@ void build_plan(pdt_problem_s* pb, int prec, int scaling, const std::vector<doub
     Instance& I = pb->inst[k];
     BatchInst<T> bi;
     bi.pv = view_var(I, var);
+    bi.pv.fx_split = 1;  // batches run one workgroup per probe tile
     bi.b = bufs_of(I, work_of<T>(I), nullptr, scaling == PDT_STEP_DIAG ? I.wrow : nullptr);
+    bi.b.fx_part = nullptr;
+    bi.b.fx_count = nullptr;
     bi.st = I.st;
     bi.step = steps[k];
-    bi.n_dt = fx_num_waves(bi.pv);
+    bi.n_dt = fx_num_tiles(bi.pv);
     bi.n_mt = ftr_num_waves(bi.pv);
     host[k] = bi;
     const int nt = (int)(I.Npad / 16);

@@ -72,6 +72,7 @@ struct ProbView {
   double gamma;
   int ks_fx = 4;   // waves per workgroup of the forward product (4 or 8)
   int ks_ftr = 4;  // waves per workgroup of the transposed product (4 or 8)
+  int fx_split = 1;  // workgroups sharing one 16-probe tile of the forward product
 };
 
 template <typename T>
@@ -88,6 +89,8 @@ struct Bufs {
   const double* wrow = nullptr;  // [M] per-row step weights (null: every row takes the step)
   float* dX = nullptr;           // [M][Npad] FP32 X_new - X_cur (mixed path: written by the
                                  // transposed product, read by the forward product)
+  double* fx_part = nullptr;     // [tiles * fx_split][16][16 NT] partial tiles (split forward product)
+  unsigned* fx_count = nullptr;  // [tiles] finished workgroups per tile, zero between launches
 };
 
 // One instance of a batched launch: its problem view, buffers, state and step; n_dt
@@ -147,6 +150,9 @@ hipError_t launch_ftr_batch(int nt, int ks, const BatchInst<TS>* insts, const in
 template <typename TS>
 hipError_t launch_decide_batch(const BatchInst<TS>* insts, int n_inst, int mode, hipStream_t s);
 
+// 16-probe tiles of the forward product; its partials (the decide kernels' count):
+// one per tile, or with a split contraction one per workgroup plus one per tile
+int fx_num_tiles(const ProbView& pv);
 int fx_num_waves(const ProbView& pv);
 int ftr_num_waves(const ProbView& pv);
 

@@ -219,7 +219,11 @@ __global__ void convert_pad_kernel(const Ts* src, Td* dst, long long rows, int c
 // ---------------------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------------------
-int fx_num_waves(const ProbView& pv) { return (pv.D + 15) / 16; }
+int fx_num_tiles(const ProbView& pv) { return (pv.D + 15) / 16; }
+int fx_num_waves(const ProbView& pv) {
+  const int t = fx_num_tiles(pv);
+  return pv.fx_split > 1 ? t * pv.fx_split + t : t;
+}
 int ftr_num_waves(const ProbView& pv) { return (pv.M + 15) / 16; }
 
 template <typename TS>

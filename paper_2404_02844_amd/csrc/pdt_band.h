@@ -80,12 +80,15 @@ __device__ __forceinline__ void wave_lds_order() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// (the first ntv of the NT column tiles: a partial last pass of the transposed product)
 template <typename T, int NT, int KS, typename AccT>
-__device__ __forceinline__ void reduce_tiles(const AccT (&acc)[NT], double* S, int ld, int wv, int i, int kq) {
+__device__ __forceinline__ void reduce_tiles(const AccT (&acc)[NT], double* S, int ld, int wv, int i, int kq,
+                                             int ntv = NT) {
   for (int w = 0; w < KS; ++w) {
     if (wv == w) {
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt)
+        if (nt < ntv)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           double* p = S + Acc<T>::row(kq, r) * ld + nt * 16 + i;
@@ -364,11 +367,18 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
   typedef TS T;
   typedef typename Acc<TC>::type AccT;
   constexpr int LDT = 16 * NT + 1;
+  // Wide rows (NT >= 8) with FP64 operands are contracted in two passes over half the
+  // column tiles each, which keeps the accumulators and the prefetch ring of one pass
+  // within the register budget of two waves per SIMD; every pass reduces into its
+  // columns of the full tile.  (FP32 operands fit two waves in one pass.)
+  constexpr int NTC = (NT >= 8 && sizeof(TC) == 8) ? (NT + 1) / 2 : NT;
+  constexpr int NPASS = (NT + NTC - 1) / NTC;
   // the F^T staging tiles of the main loop and the reduction tile share one LDS block
+  // (a single pass), or sit side by side (two passes)
   constexpr int kFt = KS * kChunkD * 17, kS = 16 * LDT;
-  __shared__ double lds[kFt > kS ? kFt : kS];
+  __shared__ double lds[NPASS > 1 ? kFt + kS : (kFt > kS ? kFt : kS)];
   double(*Ft)[kChunkD][17] = reinterpret_cast<double(*)[kChunkD][17]>(lds);
-  double* S = lds;
+  double* S = NPASS > 1 ? lds + kFt : lds;
   __shared__ double red[KS];
 
   const int tid = threadIdx.x;
@@ -383,16 +393,13 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
   const int dhi = pv.mt_dhi[mt];
   const T* __restrict__ R = (mode == FTR_STEP && st->sel_acc) ? b.R_acc : b.R_rej;
 
-  AccT acc[NT];
-#pragma unroll
-  for (int nt = 0; nt < NT; ++nt) acc[nt] = AccT{0, 0, 0, 0};
-
   // probes beyond dhi are clamped: their generated F entries are zero
-  auto load_r = [&](int drow, TC (&dst)[NT]) {
+  auto load_r = [&](int drow, TC (&dst)[NTC], int nt0) {
     const int dd = drow < dhi ? drow : dhi;
     const unsigned base = (unsigned)(dd > 0 ? dd : 0) * (unsigned)Npad + (unsigned)i;
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) dst[nt] = (TC)R[base + 16u * nt];
+    for (int k = 0; k < NTC; ++k)
+      if (NPASS == 1 || nt0 + k < NT) dst[k] = (TC)R[base + 16u * (nt0 + k)];
   };
   const int nchunks = dhi >= dlo ? (dhi - dlo) / kChunkD + 1 : 0;
   const int rounds = (nchunks + KS - 1) / KS;
@@ -430,10 +437,6 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
     return f;
   };
 
-  int dc = dlo + kChunkD * wv;
-  TC rb[PF][NT];
-#pragma unroll
-  for (int p = 0; p < PF; ++p) load_r(dc + 16 * kq + p, rb[p]);
 
   // The epilogue's inputs that do not depend on the contraction -- Y = X + beta (X -
   // X_prev) and its Laplacian along m for this group's row -- are loaded and formed here,
@@ -471,42 +474,54 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
       for (int nt = 0; nt < NT; ++nt) form_y(nt, hx[nt], hy[nt], hly[nt]);
     }
   }
-  double vals[16];
-  Gen gn;  // parameters of the chunk after the one being generated
-  if (rounds > 0) {
-    Gen g = gen_params(dc);
-    gen_anchor(g);
+#pragma unroll 1
+  for (int pass = 0; pass < NPASS; ++pass) {
+    const int nt0 = pass * NTC;
+    AccT acc[NTC];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) vals[j] = gen_step(g, j);
-    gn = gen_params(dc + stride);
-  }
-  // Each wave stages only its own Ft[wv] slice, so the waves need no barrier between
-  // rounds: a wave's LDS operations complete in issue order, and wave_lds_order() keeps
-  // the compiler from moving them across each other.
-  for (int rd = 0; rd < rounds; ++rd, dc += stride) {
-    const int dcn = dc + stride;
+    for (int k = 0; k < NTC; ++k) acc[k] = AccT{0, 0, 0, 0};
+    int dc = dlo + kChunkD * wv;
+    TC rb[PF][NTC];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) Ft[wv][lane][j] = vals[j];
-    wave_lds_order();
-    // the next chunk's F values are generated between this chunk's MFMAs
-    Gen g = gn;
+    for (int p = 0; p < PF; ++p) load_r(dc + 16 * kq + p, rb[p], nt0);
+    double vals[16];
+    Gen gn;  // parameters of the chunk after the one being generated
+    if (rounds > 0) {
+      Gen g = gen_params(dc);
+      gen_anchor(g);
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const TC a = (TC)Ft[wv][16 * kq + s][i];
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) acc[nt] = Acc<TC>::mfma(a, rb[s % PF][nt], acc[nt]);
-      if (s + PF < 16) load_r(dc + 16 * kq + s + PF, rb[s % PF]);
-      else load_r(dcn + 16 * kq + s + PF - 16, rb[s % PF]);
-      if (s == 1) gen_anchor(g);
-      if (s == 2) gn = gen_params(dcn + stride);
-      if (s >= 2) vals[s - 2] = gen_step(g, s - 2);
+      for (int j = 0; j < 16; ++j) vals[j] = gen_step(g, j);
+      gn = gen_params(dc + stride);
     }
-    vals[14] = gen_step(g, 14);
-    vals[15] = gen_step(g, 15);
-    wave_lds_order();
+    // Each wave stages only its own Ft[wv] slice, so the waves need no barrier between
+    // rounds: a wave's LDS operations complete in issue order, and wave_lds_order() keeps
+    // the compiler from moving them across each other.
+    for (int rd = 0; rd < rounds; ++rd, dc += stride) {
+      const int dcn = dc + stride;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) Ft[wv][lane][j] = vals[j];
+      wave_lds_order();
+      // the next chunk's F values are generated between this chunk's MFMAs
+      Gen g = gn;
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const TC a = (TC)Ft[wv][16 * kq + s][i];
+#pragma unroll
+        for (int k = 0; k < NTC; ++k)
+          if (NPASS == 1 || nt0 + k < NT) acc[k] = Acc<TC>::mfma(a, rb[s % PF][k], acc[k]);
+        if (s + PF < 16) load_r(dc + 16 * kq + s + PF, rb[s % PF], nt0);
+        else load_r(dcn + 16 * kq + s + PF - 16, rb[s % PF], nt0);
+        if (s == 1) gen_anchor(g);
+        if (s == 2) gn = gen_params(dcn + stride);
+        if (s >= 2) vals[s - 2] = gen_step(g, s - 2);
+      }
+      vals[14] = gen_step(g, 14);
+      vals[15] = gen_step(g, 15);
+      wave_lds_order();
+    }
+    __syncthreads();  // a single pass: S shares its LDS with every wave's Ft slice
+    reduce_tiles<TC, NTC, KS>(acc, S + 16 * nt0, LDT, wv, i, kq, NT - nt0);
   }
-  __syncthreads();  // S shares its LDS with every wave's Ft slice
-  reduce_tiles<TC, NT, KS>(acc, S, LDT, wv, i, kq);
 
   // epilogue: wave wv finishes rows m0 + 4 wv + kq (one row per 16-lane group)
   const T g2 = (T)(2.0 * pv.gamma);

@@ -146,25 +146,29 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
   const int mlo = pv.dt_mlo[tile];
   const int mhi = pv.dt_mhi[tile];
 
-  AccT acc[NT];
-#pragma unroll
-  for (int nt = 0; nt < NT; ++nt) acc[nt] = AccT{0, 0, 0, 0};
+  // Wide rows (NT >= 8) with FP64 operands run the contraction in two passes over half
+  // the column tiles each (accumulators and prefetch ring of one pass within two waves
+  // per SIMD); each pass restarts the recursion from its anchors.
+  constexpr int NTC = (NT >= 8 && sizeof(TC) == 8) ? (NT + 1) / 2 : NT;
+  constexpr int NPASS = (NT + NTC - 1) / NTC;
 
   // Contraction step s of a 64-photon-number chunk at mb gives k-slot kq the photon
   // number mb + 4 s + kq, so each lane walks its probe's row of F with stride 4 across
   // the wave's whole (contiguous) share of the tile: F[d][m + 4] = F[d][m] mu^4 r4[m],
   // r4[m] = 1 / ((m+1)(m+2)(m+3)(m+4)).  A lane takes a fresh anchor where its band
   // starts and every 16 chunks.  X rows beyond M-1 are clamped: F is zero there.
-  auto load_step = [&](int mrow, TC (&dst)[NT], double& r) {
+  auto load_step = [&](int mrow, TC (&dst)[NTC], double& r, int nt0) {
     const int m = mrow < M - 1 ? mrow : M - 1;
     const unsigned base = (unsigned)m * (unsigned)Npad + (unsigned)i;
     if constexpr (delta) {
       // the candidate step, written in FP32 by the transposed product's epilogue
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) dst[nt] = (TC)b.dX[base + 16u * nt];
+      for (int k = 0; k < NTC; ++k)
+        if (NPASS == 1 || nt0 + k < NT) dst[k] = (TC)b.dX[base + 16u * (nt0 + k)];
     } else {
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) dst[nt] = (TC)X[base + 16u * nt];
+      for (int k = 0; k < NTC; ++k)
+        if (NPASS == 1 || nt0 + k < NT) dst[k] = (TC)X[base + 16u * (nt0 + k)];
     }
     r = pv.r4[mrow];
   };
@@ -193,11 +197,11 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
       }
     }
   }
-  TC xb[PF][NT];
+  TC xb[PF][NTC];
   double rb[PF];
   if (c0 < c1) {
 #pragma unroll
-    for (int q = 0; q < PF; ++q) load_step(mlo + kChunkM * c0 + 4 * q + kq, xb[q], rb[q]);
+    for (int q = 0; q < PF; ++q) load_step(mlo + kChunkM * c0 + 4 * q + kq, xb[q], rb[q], 0);
   }
 
   // Work of the epilogue that does not depend on the contraction is done here so that its
@@ -232,36 +236,48 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
       }
     }
   }
-  double p = 0.0;
-  // blocks of 16 chunks; the recursion restarts from an exact anchor at each block after
-  // the band-start chunk, which bounds the growth of its rounding error
 #pragma unroll 1
-  for (int cblk = c0; cblk < c1; cblk += 16) {
-    if (cb >= 0 && cblk > cb) {
-      const int ma = mlo + kChunkM * cblk + kq;
-      if (ma <= bhi && ma + 60 >= blo) p = poisson_pmf(ma, mu);
+  for (int pass = 0; pass < NPASS; ++pass) {
+    const int nt0 = pass * NTC;
+    if (pass > 0 && c0 < c1) {
+#pragma unroll
+      for (int q = 0; q < PF; ++q) load_step(mlo + kChunkM * c0 + 4 * q + kq, xb[q], rb[q], nt0);
     }
-    const int cend = cblk + 16 < c1 ? cblk + 16 : c1;
-    for (int c = cblk; c < cend; ++c) {
-      const int mb = mlo + kChunkM * c;
-      const bool more = c + 1 < c1;
-      const int ma = mb + kq;
-      if (c == cb) p = p_start;
+    AccT acc[NTC];
 #pragma unroll
-      for (int st = 0; st < 16; ++st) {
-        const int m = ma + 4 * st;
-        double f = (m >= blo && m <= bhi) ? p : 0.0;
-        f = (m == lumpm && m >= blo && m <= bhi) ? tl : f;
-        p *= mu4 * rb[st % PF];
-        const TC a = (TC)f;
+    for (int k = 0; k < NTC; ++k) acc[k] = AccT{0, 0, 0, 0};
+    double p = 0.0;
+    // blocks of 16 chunks; the recursion restarts from an exact anchor at each block after
+    // the band-start chunk, which bounds the growth of its rounding error
+#pragma unroll 1
+    for (int cblk = c0; cblk < c1; cblk += 16) {
+      if (cb >= 0 && cblk > cb) {
+        const int ma = mlo + kChunkM * cblk + kq;
+        if (ma <= bhi && ma + 60 >= blo) p = poisson_pmf(ma, mu);
+      }
+      const int cend = cblk + 16 < c1 ? cblk + 16 : c1;
+      for (int c = cblk; c < cend; ++c) {
+        const int mb = mlo + kChunkM * c;
+        const bool more = c + 1 < c1;
+        const int ma = mb + kq;
+        if (c == cb) p = p_start;
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[nt] = Acc<TC>::mfma(a, xb[st % PF][nt], acc[nt]);
-        if (st + PF < 16) load_step(m + 4 * PF, xb[st % PF], rb[st % PF]);
-        else if (more) load_step(m + 4 * PF, xb[st % PF], rb[st % PF]);
+        for (int st = 0; st < 16; ++st) {
+          const int m = ma + 4 * st;
+          double f = (m >= blo && m <= bhi) ? p : 0.0;
+          f = (m == lumpm && m >= blo && m <= bhi) ? tl : f;
+          p *= mu4 * rb[st % PF];
+          const TC a = (TC)f;
+#pragma unroll
+          for (int k = 0; k < NTC; ++k)
+            if (NPASS == 1 || nt0 + k < NT) acc[k] = Acc<TC>::mfma(a, xb[st % PF][k], acc[k]);
+          if (st + PF < 16) load_step(m + 4 * PF, xb[st % PF], rb[st % PF], nt0);
+          else if (more) load_step(m + 4 * PF, xb[st % PF], rb[st % PF], nt0);
+        }
       }
     }
+    reduce_tiles<TC, NTC, KS>(acc, S + 16 * nt0, LDT, wv, i, kq, NT - nt0);
   }
-  reduce_tiles<TC, NT, KS>(acc, S, LDT, wv, i, kq);
 
   if (nsplit > 1) {
     constexpr int kTile = 16 * 16 * NT;
@@ -609,8 +625,10 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
 }
 
 
+// two waves per SIMD: the forward product's loads and recursion are latency-bound
 template <typename TS, typename TC, int NT, int KS>
-__global__ __launch_bounds__(64 * KS) void fx_kernel(ProbView pv, Bufs<TS> b, SolverState* st, int mode) {
+__global__ __launch_bounds__(64 * KS) __attribute__((amdgpu_waves_per_eu(2))) void fx_kernel(ProbView pv, Bufs<TS> b,
+                                                                                            SolverState* st, int mode) {
   fx_body<TS, TC, NT, KS>(pv, b, st, mode, blockIdx.x, gridDim.x);
 }
 

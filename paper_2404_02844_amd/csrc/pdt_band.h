@@ -286,7 +286,9 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
     double rp = (pv.gamma != 0.0 && M > 1) ? pv.gamma * reg : 0.0;
     rp = group_sum<64>(rp);
     if (lane == 0) red[wv] = rp;
-    __threadfence();  // this thread's share of the partial tile, visible device-wide
+    // Every wave's stores have completed at the barrier; one device-scope release by one
+    // thread then publishes the workgroup's partial tile (a device-scope fence writes the
+    // XCD's L2 back, so it is issued once per workgroup, not once per thread).
     __syncthreads();
     __shared__ int is_last;
     if (tid == 0) {
@@ -294,13 +296,16 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
 #pragma unroll
       for (int w = 0; w < KS; ++w) sr += red[w];
       b.partials[wg] = sr;
+      __threadfence();
       const unsigned prev = atomicAdd(&b.fx_count[tile], 1u);
       is_last = prev == (unsigned)(nsplit - 1);
-      if (is_last) b.fx_count[tile] = 0u;  // ready for the next launch
+      if (is_last) {
+        b.fx_count[tile] = 0u;  // ready for the next launch
+        __threadfence();        // acquire: the other workgroups' partial tiles
+      }
     }
     __syncthreads();
     if (!is_last) return;
-    __threadfence();  // the other workgroups' partial tiles are visible from here on
     const double* parts = b.fx_part + (size_t)tile * nsplit * kTile;
     for (int q = tid; q < kTile; q += 64 * KS) {
       double v = 0.0;

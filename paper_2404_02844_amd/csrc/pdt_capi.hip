@@ -93,7 +93,7 @@ struct NewtonWork {
   double* Rh = nullptr;   // [D][Npad] F Vf (the transposed product's operand)
   double* Pz = nullptr;   // [D][Npad] zeros: the data term of a Hessian product
   double* Rg = nullptr;   // [D][Npad] F X - P of the last evaluated point
-  double* part = nullptr;  // [2 kNtBlocks] row-kernel partials
+  double* part = nullptr;  // [4 kNtBlocks] row-kernel partials
   double* bpart = nullptr;  // band-kernel partials
   uint8_t* mask = nullptr;
   int* mi = nullptr;       // [M] row maxima of stage 2
@@ -703,7 +703,7 @@ NewtonWork& ensure_newton(pdt_problem_s* pb, Instance& I) {
   nw.Rh = A.alloc<double>(od);
   nw.Pz = A.alloc<double>(od);
   nw.Rg = A.alloc<double>(od);
-  nw.part = A.alloc<double>(2 * kNtBlocks);
+  nw.part = A.alloc<double>(4 * kNtBlocks);
   nw.bpart = A.alloc<double>((size_t)I.n_partials);
   nw.mask = A.alloc<uint8_t>(xm);
   nw.mi = A.alloc<int>((size_t)I.M);
@@ -780,8 +780,8 @@ int nt_direction(const ProbView& pv, const Instance& I, NewtonWork& nw, const Nt
   for (int it = 0; it < cg_max; ++it) {
     nt_hessian(pv, I, nw, nw.Vf, nw.Gh, s);
     HIPCHK(launch_nt_q(rows, nw.mask, nw.mi, I.hdiag, nw.p, nw.Gh, nw.q, nw.part, nw.ns, s));
-    HIPCHK(launch_nt_update(rows, nw.mask, I.hdiag, nw.Dir, nw.res, nw.z, nw.p, nw.q, nw.part, nw.ns, s));
-    HIPCHK(launch_nt_dir(rows, nw.mask, nw.mi, nw.z, nw.p, nw.Vf, nw.ns, s));
+    HIPCHK(launch_nt_update(rows, nw.mask, I.hdiag, nw.Dir, nw.res, nw.z, nw.p, nw.q, nw.part, nw.ns, it & 1, s));
+    HIPCHK(launch_nt_dir(rows, nw.mask, nw.mi, nw.z, nw.p, nw.Vf, nw.part, nw.ns, it & 1, s));
     const int slot = it & 1;
     HIPCHK(hipMemcpyAsync(&nw.flag_h[slot], &nw.ns->cg_done, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(nw.ev[slot], s));

@@ -19,11 +19,9 @@ namespace pdt {
 
 // Device-resident scalars of one conjugate-gradient solve.
 struct NewtonState {
-  double rz;        // r . z of the current residual
+  double rz[2];     // r . z of the current residual (iteration k keeps it in rz[k % 2])
   double nr0;       // ||r_0||
   double rtol;      // stop at ||r|| <= rtol ||r_0||
-  double alpha;     // step of the current CG iteration
-  double beta;      // weight of the previous search direction
   double out[4];    // sums handed to the host
   int cg_iter;      // CG iterations started
   int cg_max;
@@ -44,11 +42,13 @@ hipError_t launch_nt_prep(const NtRows& r, const double* X, const double* G, con
                           double* part, NewtonState* ns, double rtol, int cg_max, hipStream_t s);
 hipError_t launch_nt_q(const NtRows& r, const uint8_t* mask, const int* mi, const double* h, const double* p,
                        const double* Gh, double* q, double* part, NewtonState* ns, hipStream_t s);
+// part: [4 kNtBlocks] (p'q partials first, r'r and r'z partials from 2 kNtBlocks on);
+// par = CG iteration % 2
 hipError_t launch_nt_update(const NtRows& r, const uint8_t* mask, const double* h, double* Dir, double* res,
-                            double* z, const double* p, const double* q, double* part, NewtonState* ns,
+                            double* z, const double* p, const double* q, double* part, NewtonState* ns, int par,
                             hipStream_t s);
 hipError_t launch_nt_dir(const NtRows& r, const uint8_t* mask, const int* mi, const double* z, double* p,
-                         double* Vf, NewtonState* ns, hipStream_t s);
+                         double* Vf, double* part, NewtonState* ns, int par, hipStream_t s);
 hipError_t launch_nt_slope(const NtRows& r, const double* X, const double* Dir, const double* G, const int* mi,
                            double* part, NewtonState* ns, hipStream_t s);
 hipError_t launch_nt_negrad(const NtRows& r, const double* G, const int* mi, double* Dir, hipStream_t s);

@@ -220,10 +220,8 @@ __global__ __launch_bounds__(256) void nt_cginit_kernel(const double* part, int 
   const double rz = sum_partials(part + nb, nb);
   if (threadIdx.x != 0) return;
   ns->nr0 = sqrt(rr0);
-  ns->rz = rz;
+  ns->rz[0] = rz;
   ns->rtol = rtol;
-  ns->alpha = 0.0;
-  ns->beta = 0.0;
   ns->cg_iter = 0;
   ns->cg_max = cg_max;
   ns->cg_done = (rr0 == 0.0 || cg_max <= 0) ? 1 : 0;
@@ -255,24 +253,22 @@ __global__ __launch_bounds__(256) void nt_q_kernel(NtRows r, const uint8_t* mask
   block_partials<1>(acc, part, gridDim.x);
 }
 
-__global__ __launch_bounds__(256) void nt_alpha_kernel(const double* part, int nb, NewtonState* ns) {
-  if (ns->cg_done) return;
-  const double pq = sum_partials(part, nb);
-  if (threadIdx.x != 0) return;
-  ns->cg_iter += 1;
-  if (!(pq > 0.0)) {
-    ns->cg_done = 1;  // D is not positive definite along p: keep the current solution
-    return;
-  }
-  ns->alpha = ns->rz / pq;
-}
-
+// CG step of iteration k (par = k % 2): every block forms p'q from the q kernel's
+// partials in the same fixed order, so all blocks take the same alpha = r'z / p'q and
+// the same decision; block 0 records it.  r'z of iteration k sits in rz[par].
 template <int V>
 __global__ __launch_bounds__(256) void nt_update_kernel(NtRows r, const uint8_t* mask, const double* h, double* Dir,
                                                         double* res, double* z, const double* p, const double* q,
-                                                        double* part, const NewtonState* ns) {
+                                                        const double* part_pq, double* part, NewtonState* ns,
+                                                        int par) {
   if (ns->cg_done) return;
-  const double alpha = ns->alpha;
+  const double pq = sum_partials(part_pq, gridDim.x);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ns->cg_iter += 1;
+    if (!(pq > 0.0)) ns->cg_done = 1;  // D is not positive definite along p: keep the current solution
+  }
+  if (!(pq > 0.0)) return;
+  const double alpha = ns->rz[par] / pq;
   double acc[2] = {0.0, 0.0};
   NT_ROWS(r) {
     const size_t base = (size_t)m * r.Npad;
@@ -294,24 +290,23 @@ __global__ __launch_bounds__(256) void nt_update_kernel(NtRows r, const uint8_t*
   block_partials<2>(acc, part, gridDim.x);
 }
 
-__global__ __launch_bounds__(256) void nt_beta_kernel(const double* part, int nb, NewtonState* ns) {
-  if (ns->cg_done) return;
-  const double rr = sum_partials(part, nb);
-  const double rzn = sum_partials(part + nb, nb);
-  if (threadIdx.x != 0) return;
-  if (sqrt(rr) <= ns->rtol * ns->nr0 || ns->cg_iter >= ns->cg_max) {
-    ns->cg_done = 1;
-    return;
-  }
-  ns->beta = rzn / ns->rz;
-  ns->rz = rzn;
-}
-
+// Next search direction: every block forms r'r and r'z from the update's partials in the
+// same fixed order and takes the same stopping decision and beta = r'z_new / r'z; block 0
+// records r'z_new in rz[par ^ 1] (rz[par] stays readable for the other blocks).
 template <int V>
 __global__ __launch_bounds__(256) void nt_dir_kernel(NtRows r, const uint8_t* mask, const int* mi_in, const double* z,
-                                                     double* p, double* Vf, const NewtonState* ns) {
+                                                     double* p, double* Vf, const double* part, NewtonState* ns,
+                                                     int par) {
   if (ns->cg_done) return;
-  const double beta = ns->beta;
+  const double rr = sum_partials(part, gridDim.x);
+  const double rzn = sum_partials(part + gridDim.x, gridDim.x);
+  const bool stop = sqrt(rr) <= ns->rtol * ns->nr0 || ns->cg_iter >= ns->cg_max;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (stop) ns->cg_done = 1;
+    else ns->rz[par ^ 1] = rzn;
+  }
+  if (stop) return;
+  const double beta = rzn / ns->rz[par];
   NT_ROWS(r) {
     const size_t base = (size_t)m * r.Npad;
     const int mi = r.stage == 2 ? mi_in[m] : -1;
@@ -563,26 +558,28 @@ hipError_t launch_nt_q(const NtRows& r, const uint8_t* mask, const int* mi, cons
 #define K_(V) hipLaunchKernelGGL((nt_q_kernel<V>), dim3(nb), dim3(256), 0, s, r, mask, mi, h, p, Gh, q, part, ns)
   NT_V_SWITCH(r, K_)
 #undef K_
-  hipLaunchKernelGGL(nt_alpha_kernel, dim3(1), dim3(256), 0, s, part, nb, ns);
   return hipGetLastError();
 }
 
 hipError_t launch_nt_update(const NtRows& r, const uint8_t* mask, const double* h, double* Dir, double* res,
-                            double* z, const double* p, const double* q, double* part, NewtonState* ns,
+                            double* z, const double* p, const double* q, double* part, NewtonState* ns, int par,
                             hipStream_t s) {
   const int nb = nt_blocks(r);
-#define K_(V) \
-  hipLaunchKernelGGL((nt_update_kernel<V>), dim3(nb), dim3(256), 0, s, r, mask, h, Dir, res, z, p, q, part, ns)
+  // p'q partials of the q kernel in part[0, nb); r'r and r'z partials into part[2 kNtBlocks, ...)
+#define K_(V)                                                                                                    \
+  hipLaunchKernelGGL((nt_update_kernel<V>), dim3(nb), dim3(256), 0, s, r, mask, h, Dir, res, z, p, q, part,      \
+                     part + 2 * kNtBlocks, ns, par)
   NT_V_SWITCH(r, K_)
 #undef K_
-  hipLaunchKernelGGL(nt_beta_kernel, dim3(1), dim3(256), 0, s, part, nb, ns);
   return hipGetLastError();
 }
 
 hipError_t launch_nt_dir(const NtRows& r, const uint8_t* mask, const int* mi, const double* z, double* p,
-                         double* Vf, NewtonState* ns, hipStream_t s) {
+                         double* Vf, double* part, NewtonState* ns, int par, hipStream_t s) {
   const int nb = nt_blocks(r);
-#define K_(V) hipLaunchKernelGGL((nt_dir_kernel<V>), dim3(nb), dim3(256), 0, s, r, mask, mi, z, p, Vf, ns)
+#define K_(V)                                                                                                    \
+  hipLaunchKernelGGL((nt_dir_kernel<V>), dim3(nb), dim3(256), 0, s, r, mask, mi, z, p, Vf, part + 2 * kNtBlocks, \
+                     ns, par)
   NT_V_SWITCH(r, K_)
 #undef K_
   return hipGetLastError();

@@ -78,6 +78,16 @@ def test_c3_gradient_rows(c3):
     assert np.max(np.abs(got - G_rows)) <= 1e-10 * scale
 
 
+def test_c3_hessian_rows(c3):
+    # Newton-CG's Hessian product at full size: the gradient of the same point against
+    # zero data, from the row-at-a-time oracle
+    inst, pb, ro, Pi, _ = c3
+    HV = torch.empty((inst.M, inst.N), dtype=torch.float64, device="cuda")
+    pb.hessian(torch.as_tensor(Pi, device="cuda"), HV)
+    ref = ro.gradient_rows(np.zeros_like(inst.P), Pi, inst.gamma, ROWS)
+    assert np.max(np.abs(HV[ROWS].cpu().numpy() - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
 @pytest.mark.parametrize("precision,tol", [(_pdt.PDT_FP64, 1e-9), (_pdt.PDT_MIXED, 1e-4)])
 def test_c3_one_scaled_step(c3, precision, tol):
     # from Pi (a feasible start) the first step has no momentum:

@@ -234,7 +234,8 @@ pdt_status pdt_problem_fx_split(pdt_problem_t problem, int64_t instance, int* sp
  * of App. B (Algorithms 1-3) on instance 0.
  *
  * Stage 1 (Algorithm 2): binding set I = {Pi <= eps, df/dPi > 0} (Eq. 2metric_I) with
- * eps = min(1e-3, ||Pi - P_S(Pi - grad)||); direction from D P = -grad, D the Hessian
+ * eps = min(eps_cap, ||Pi - P_S(Pi - grad)||) (eps_cap 1e-9 by default; stage 2 uses the
+ * residual of the bound constraints); direction from D P = -grad, D the Hessian
  * 2 F^T F + 2 gamma L_path on the free entries and its diagonal on I, solved by
  * conjugate gradients preconditioned with the Hessian diagonal (Hessian products are
  * the band kernels of pdt_solve); Armijo search (beta 3/4, c 1/10) on
@@ -267,6 +268,7 @@ typedef struct {
   double* history;        /* host [max_newton + 1] or NULL */
   double f_star;          /* known optimum value; <= 0 disables the objective test */
   double rel_obj_tol;     /* also stop once f - f_star <= rel_obj_tol * f_star */
+  double eps_cap;         /* binding tolerance eps = min(eps_cap, w) (0: 1e-9) */
 } pdt_newton_opts;
 
 typedef struct {

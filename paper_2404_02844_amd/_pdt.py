@@ -69,7 +69,7 @@ class pdt_newton_opts(ctypes.Structure):
     _fields_ = [("max_newton", ctypes.c_int64), ("eps_kkt", ctypes.c_double), ("stage_switch", ctypes.c_double),
                 ("cg_rtol", ctypes.c_double), ("cg_max", ctypes.c_int32), ("init", ctypes.c_int32),
                 ("stage2_only", ctypes.c_int32), ("history", ctypes.c_void_p), ("f_star", ctypes.c_double),
-                ("rel_obj_tol", ctypes.c_double)]
+                ("rel_obj_tol", ctypes.c_double), ("eps_cap", ctypes.c_double)]
 
 
 class pdt_newton_info(ctypes.Structure):
@@ -233,7 +233,7 @@ def pdt_kkt(handle, Pi) -> float:
 
 def pdt_newton_solve(handle, Pi, *, max_newton=200, eps_kkt=1e-10, stage_switch=1e-4, cg_rtol=1e-4, cg_max=50,
                      init=PDT_INIT_UNIFORM, stage2_only=False, history=None, f_star=0.0, rel_obj_tol=0.0,
-                     allow_not_converged=True) -> dict:
+                     eps_cap=1e-9, allow_not_converged=True) -> dict:
     """Two-stage Newton solve in place: ``Pi`` is a contiguous float64 [M, N] GPU tensor.
     ``history``: optional float64 numpy array of at least max_newton + 1 entries."""
     import numpy as np
@@ -243,7 +243,7 @@ def pdt_newton_solve(handle, Pi, *, max_newton=200, eps_kkt=1e-10, stage_switch=
     o = pdt_newton_opts(max_newton=int(max_newton), eps_kkt=float(eps_kkt), stage_switch=float(stage_switch),
                         cg_rtol=float(cg_rtol), cg_max=int(cg_max), init=int(init), stage2_only=int(bool(stage2_only)),
                         history=history.ctypes.data_as(ctypes.c_void_p) if history is not None else None,
-                        f_star=float(f_star), rel_obj_tol=float(rel_obj_tol))
+                        f_star=float(f_star), rel_obj_tol=float(rel_obj_tol), eps_cap=float(eps_cap))
     info = pdt_newton_info()
     st = _check(lib().pdt_newton_solve(handle, ctypes.c_void_p(Pi.data_ptr()), ctypes.byref(o), ctypes.byref(info)),
                 allow=(PDT_ERR_NOT_CONVERGED,) if allow_not_converged else ())

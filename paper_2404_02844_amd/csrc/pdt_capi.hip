@@ -838,7 +838,7 @@ void newton_run(pdt_problem_s* pb, Instance& I, const pdt_newton_opts& o, Newton
       out.converged = true;
       break;
     }
-    const double eps = std::min(1e-3, std::sqrt(m.out[1]));
+    const double eps = std::min(o.eps_cap > 0.0 ? o.eps_cap : 1e-9, std::sqrt(m.out[1]));
     out.cg += nt_direction(pv, I, nw, rows, X, eps, o.cg_rtol, o.cg_max, s);
     double slope = nt_slope(I, nw, rows, X, s);
     if (slope >= 0.0) {
@@ -1118,6 +1118,7 @@ pdt_status pdt_newton_solve(pdt_problem_t pb, double* Pi, const pdt_newton_opts*
   if (o.stage2_only != 0 && o.stage2_only != 1) return set_err(PDT_ERR_INVALID_ARG, "stage2_only must be 0 or 1");
   if (!std::isfinite(o.f_star) || !std::isfinite(o.rel_obj_tol) || o.rel_obj_tol < 0)
     return set_err(PDT_ERR_INVALID_ARG, "bad objective tolerance");
+  if (!std::isfinite(o.eps_cap) || o.eps_cap < 0) return set_err(PDT_ERR_INVALID_ARG, "eps_cap must be >= 0");
   const auto t0 = std::chrono::steady_clock::now();
   try {
     Instance& I = pb->inst[0];

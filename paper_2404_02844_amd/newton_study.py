@@ -10,8 +10,9 @@
    its objective.
 3. The momentum method (row-scaled step) on the same problem, to the same tolerance,
    for reference.
-4. (--sweep) The stage-switch threshold and the CG budget per Newton step, varied
-   around the paper's values (|phi'(0)| <= 1e-4, 50 iterations), 800 steps each.
+4. (--sweep) The stage-switch threshold, the CG budget per Newton step and the cap of
+   the binding tolerance, varied around the paper's values (|phi'(0)| <= 1e-4, 50
+   iterations) and the Bertsekas reading (cap 1e-3), 800 steps each.
 
 Every solve runs in the HIP library; this module only sequences calls and scores.
 
@@ -113,19 +114,22 @@ def sweep(inst, dev, log) -> list:
     Pi = torch.empty((inst.M, inst.N), dtype=torch.float64, device=dev)
     f_ref = pb.solve(Pi, max_iters=30000, scaling=_pdt.PDT_STEP_DIAG)["objective"]
     out = []
-    for switch in (1e-4, 1e-6, 1e-8, 0.0):
-        for cg_max in (50, 20):
+    grid = [(sw, cg, 1e-3) for sw in (1e-4, 1e-6, 1e-8, 0.0) for cg in (50, 20)]
+    grid += [(sw, 50, cap) for sw in (1e-4, 0.0) for cap in (1e-4, 1e-6, 1e-9, 1e-14)]
+    for switch, cg_max, cap in grid:
+        if True:
             hist = np.zeros(801)
             t = time.perf_counter()
-            r = pb.newton(Pi, max_newton=800, eps_kkt=0.0, stage_switch=switch, cg_max=cg_max, history=hist)
+            r = pb.newton(Pi, max_newton=800, eps_kkt=0.0, stage_switch=switch, cg_max=cg_max, history=hist,
+                          eps_cap=cap)
             torch.cuda.synchronize()
             el = time.perf_counter() - t
             n = 1 + r["stage1_iters"] + r["stage2_iters"]
-            rec = {"stage_switch": switch, "cg_max": cg_max, "time_s": el, "stage1": r["stage1_iters"],
+            rec = {"stage_switch": switch, "cg_max": cg_max, "eps_cap": cap, "time_s": el, "stage1": r["stage1_iters"],
                    "stage2": r["stage2_iters"], "cg": r["cg_iters"], "trials": r["line_trials"],
                    "relobj": (r["objective"] - f_ref) / f_ref, "kkt": r["kkt"],
                    "steps_to": rel_steps(hist[:n], f_ref, (1e-1, 1e-2, 1e-3, 1e-4, 1e-6))}
-            log(f"[sweep] switch {switch:g} cg {cg_max}: {rec['stage1']}+{rec['stage2']} steps {el:.2f} s "
+            log(f"[sweep] switch {switch:g} cg {cg_max} eps cap {cap:g}: {rec['stage1']}+{rec['stage2']} steps {el:.2f} s "
                 f"relobj {rec['relobj']:.2e} kkt {rec['kkt']:.2e} steps_to {rec['steps_to']}")
             out.append(rec)
     pb.close()

@@ -54,6 +54,5 @@ hipError_t launch_nt_slope(const NtRows& r, const double* X, const double* Dir, 
 hipError_t launch_nt_negrad(const NtRows& r, const double* G, const int* mi, double* Dir, hipStream_t s);
 hipError_t launch_nt_trial(const NtRows& r, const double* X, const double* Dir, const int* mi, double alpha,
                            double* Xa, double* part, NewtonState* ns, hipStream_t s);
-hipError_t launch_nt_expand(const NtRows& r, const double* V, const int* mi, double* out, hipStream_t s);
 
 }  // namespace pdt

@@ -480,30 +480,6 @@ __global__ __launch_bounds__(256) void nt_trial_kernel(NtRows r, const double* X
   block_partials<1>(acc, part, gridDim.x);
 }
 
-// T v for reduced variables (stage 2) or a plain copy (stage 1); used to report the
-// change of Pi that a reduced direction stands for
-template <int V>
-__global__ __launch_bounds__(256) void nt_expand_kernel(NtRows r, const double* Vin, const int* mi_in, double* out) {
-  NT_ROWS(r) {
-    const size_t base = (size_t)m * r.Npad;
-    const int mi = r.stage == 2 ? mi_in[m] : -1;
-    double u[V];
-    double s = 0.0;
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-      const int c = 64 * v + lane;
-      u[v] = (c < r.N && c != mi) ? Vin[base + c] : 0.0;
-      s += u[v];
-    }
-    s = group_sum<64>(s);
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-      const int c = 64 * v + lane;
-      if (c < r.Npad) out[base + c] = c == mi ? -s : u[v];
-    }
-  }
-}
-
 // K consecutive arrays of nb partials -> ns->out[slot + k]
 template <int K>
 __global__ __launch_bounds__(256) void nt_sum_kernel(const double* part, int nb, NewtonState* ns, int slot) {
@@ -610,14 +586,6 @@ hipError_t launch_nt_trial(const NtRows& r, const double* X, const double* Dir, 
   NT_V_SWITCH(r, K_)
 #undef K_
   hipLaunchKernelGGL((nt_sum_kernel<1>), dim3(1), dim3(256), 0, s, part, nb, ns, 1);
-  return hipGetLastError();
-}
-
-hipError_t launch_nt_expand(const NtRows& r, const double* V, const int* mi, double* out, hipStream_t s) {
-  const int nb = nt_blocks(r);
-#define K_(VV) hipLaunchKernelGGL((nt_expand_kernel<VV>), dim3(nb), dim3(256), 0, s, r, V, mi, out)
-  NT_V_SWITCH(r, K_)
-#undef K_
   return hipGetLastError();
 }
 

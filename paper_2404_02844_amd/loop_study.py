@@ -13,7 +13,7 @@ smoothing of Eq. smoothing applied to its result, followed by a second run from 
 smoothed start (the momentum method, and a short stage-2-only Newton-CG run as in the
 paper).  Every solve runs in the HIP library; this module sequences calls and scores.
 
-    python -m paper_2404_02844_amd.loop_study --out gpurun_out/loop_study.json
+    python -m paper_2404_02844_amd.loop_study --out loop_study.json
 """
 from __future__ import annotations
 

@@ -16,7 +16,7 @@
 
 Every solve runs in the HIP library; this module only sequences calls and scores.
 
-    python -m paper_2404_02844_amd.newton_study --out gpurun_out/newton_study.json
+    python -m paper_2404_02844_amd.newton_study --out newton_study.json
 """
 from __future__ import annotations
 

@@ -111,6 +111,7 @@ template <typename TS, typename TC, int NT, int KS>
 __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode, int wg,
                                         int nwg) {
   if ((mode == FX_ITER || mode == FX_DELTA || mode == FX_EVAL_PREV || mode == FX_RESYNC) && st->done) return;
+  if (b.skip && *b.skip) return;
   const int nsplit = pv.fx_split;
   const int tile = wg / nsplit;
   const int sidx = wg - tile * nsplit;
@@ -385,6 +386,7 @@ template <typename TS, typename TC, int NT, int KS>
 __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode,
                                          double step, int mt) {
   if (mode == FTR_STEP && st->done) return;
+  if (b.skip && *b.skip) return;
   typedef TS T;
   typedef typename Acc<TC>::type AccT;
   constexpr int LDT = 16 * NT + 1;

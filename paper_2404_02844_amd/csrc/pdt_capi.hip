@@ -99,8 +99,10 @@ struct NewtonWork {
   int* mi = nullptr;       // [M] row maxima of stage 2
   NewtonState* ns = nullptr;
   SolverState* st = nullptr;  // ix_cur = 0, never done: plain evaluations
-  int* flag_h = nullptr;      // pinned host [2]: CG completion flags
+  int* flag_h = nullptr;      // pinned, coherent host [2]: CG completion flags
+  int* flag_d = nullptr;      // their device address
   hipEvent_t ev[2] = {nullptr, nullptr};
+  hipGraphExec_t cg_graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [stage - 1][flag slot]
 };
 
 struct Instance {
@@ -574,6 +576,11 @@ void drop_graphs(Instance& I) {
     if (I.graph[v]) (void)hipGraphExecDestroy(I.graph[v]);
     I.graph[v] = nullptr;
   }
+  for (auto& row : I.nw.cg_graph)
+    for (hipGraphExec_t& g : row) {
+      if (g) (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
 }
 
 // One graph = kGraphIters iterations of a variant.  The mixed variant forms F X_new by
@@ -713,7 +720,11 @@ NewtonWork& ensure_newton(pdt_problem_s* pb, Instance& I) {
   HIPCHK(hipMemsetAsync(nw.mi, 0, (size_t)I.M * sizeof(int), s));
   HIPCHK(hipMemsetAsync(nw.ns, 0, sizeof(NewtonState), s));
   init_state(s, nw.st, 0, 0.0, 0.0);
-  if (!nw.flag_h) HIPCHK(hipHostMalloc((void**)&nw.flag_h, 2 * sizeof(int), hipHostMallocDefault));
+  if (!nw.flag_h) {
+    HIPCHK(hipHostMalloc((void**)&nw.flag_h, 2 * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
+    nw.flag_h[0] = nw.flag_h[1] = 0;
+    HIPCHK(hipHostGetDevicePointer((void**)&nw.flag_d, nw.flag_h, 0));
+  }
   for (hipEvent_t& e : nw.ev)
     if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   nw.ready = true;
@@ -722,7 +733,7 @@ NewtonWork& ensure_newton(pdt_problem_s* pb, Instance& I) {
 
 // Band-kernel view of one array as the current iterate of a plain evaluation.
 Bufs<double> nt_bufs(const Instance& I, const NewtonWork& nw, const double* X, double* O, const double* P, double* R,
-                     double* G) {
+                     double* G, const int* skip = nullptr) {
   Bufs<double> b;
   for (int k = 0; k < 3; ++k) {
     b.X[k] = const_cast<double*>(X);
@@ -737,13 +748,16 @@ Bufs<double> nt_bufs(const Instance& I, const NewtonWork& nw, const double* X, d
   b.history = nullptr;
   b.fx_part = I.fx_part;
   b.fx_count = I.fx_count;
+  b.skip = skip;
   return b;
 }
 
 // HV = 2 F^T (F V) + 2 gamma L V: forward product against zero data, then the transposed
-// product's gradient mode on the result.
-void nt_hessian(const ProbView& pv, const Instance& I, NewtonWork& nw, const double* V, double* HV, hipStream_t s) {
-  const Bufs<double> b = nt_bufs(I, nw, V, nw.Oh, nw.Pz, nw.Rh, HV);
+// product's gradient mode on the result.  skip (may be null): both launches return at
+// once while *skip != 0.
+void nt_hessian(const ProbView& pv, const Instance& I, NewtonWork& nw, const double* V, double* HV, const int* skip,
+                hipStream_t s) {
+  const Bufs<double> b = nt_bufs(I, nw, V, nw.Oh, nw.Pz, nw.Rh, HV, skip);
   HIPCHK(launch_fx<double>(pv, b, nw.st, FX_EVAL, s));
   HIPCHK(launch_ftr<double>(pv, b, nw.st, FTR_GRAD, 0.0, s));
 }
@@ -771,21 +785,67 @@ NewtonState nt_read(hipStream_t s, const NewtonWork& nw, double* f_eval = nullpt
   return h;
 }
 
+// One CG iteration of parity par: the Hessian product of the free part of p (skipped
+// once the solve has stopped) and the three row kernels; the direction kernel reports
+// the completion state to flag slot `slot`.
+void enqueue_cg_iter(const ProbView& pv, const Instance& I, NewtonWork& nw, const NtRows& rows, int par, int slot,
+                     hipStream_t s) {
+  nt_hessian(pv, I, nw, nw.Vf, nw.Gh, &nw.ns->cg_done, s);
+  HIPCHK(launch_nt_q(rows, nw.mask, nw.mi, I.hdiag, nw.p, nw.Gh, nw.q, nw.part, nw.ns, s));
+  HIPCHK(launch_nt_update(rows, nw.mask, I.hdiag, nw.Dir, nw.res, nw.z, nw.p, nw.q, nw.part, nw.ns, par, s));
+  HIPCHK(launch_nt_dir(rows, nw.mask, nw.mi, nw.z, nw.p, nw.Vf, nw.part, nw.ns, par, nw.flag_d + slot, s));
+}
+
+constexpr int kCgGraphIters = 4;  // CG iterations per captured launch (even: parities repeat)
+
+// kCgGraphIters CG iterations of one stage reporting to one flag slot, recorded once per
+// problem on the library's capture stream (dropped with the other graphs when the
+// kernel grid changes)
+hipGraphExec_t cg_graph(pdt_problem_s* pb, const ProbView& pv, const Instance& I, NewtonWork& nw,
+                        const NtRows& rows, int slot) {
+  hipGraphExec_t& ge = nw.cg_graph[rows.stage - 1][slot];
+  if (ge) return ge;
+  if (!pb->capture) HIPCHK(hipStreamCreateWithFlags(&pb->capture, hipStreamNonBlocking));
+  hipStream_t cs = pb->capture;
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  try {
+    for (int j = 0; j < kCgGraphIters; ++j) enqueue_cg_iter(pv, I, nw, rows, j & 1, slot, cs);
+  } catch (...) {
+    (void)hipStreamEndCapture(cs, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  HIPCHK(hipStreamEndCapture(cs, &g));
+  hipGraphExec_t e_out = nullptr;
+  const hipError_t e = hipGraphInstantiate(&e_out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIPCHK(e);
+  ge = e_out;
+  return ge;
+}
+
 // Direction of one Newton step at X (gradient in nw.G): codes, CG solve, result in
-// nw.Dir (and the row maxima in nw.mi for stage 2).  Returns the CG iterations.
-int nt_direction(const ProbView& pv, const Instance& I, NewtonWork& nw, const NtRows& rows, const double* X,
-                 double eps, double rtol, int cg_max, hipStream_t s) {
+// nw.Dir (and the row maxima in nw.mi for stage 2).  Returns the CG iterations.  The
+// iterations go out kCgGraphIters per graph launch (the last < kCgGraphIters one by
+// one); the host reads the completion flag of the previous launch only, so the device
+// always has the next one queued, and launches queued after the solve stopped return at
+// once on the device flag.
+int nt_direction(pdt_problem_s* pb, const ProbView& pv, const Instance& I, NewtonWork& nw, const NtRows& rows,
+                 const double* X, double eps, double rtol, int cg_max, hipStream_t s) {
   HIPCHK(launch_nt_prep(rows, X, nw.G, I.hdiag, eps, nw.mask, nw.mi, nw.res, nw.z, nw.p, nw.Vf, nw.Dir, nw.part,
                         nw.ns, rtol, cg_max, s));
-  for (int it = 0; it < cg_max; ++it) {
-    nt_hessian(pv, I, nw, nw.Vf, nw.Gh, s);
-    HIPCHK(launch_nt_q(rows, nw.mask, nw.mi, I.hdiag, nw.p, nw.Gh, nw.q, nw.part, nw.ns, s));
-    HIPCHK(launch_nt_update(rows, nw.mask, I.hdiag, nw.Dir, nw.res, nw.z, nw.p, nw.q, nw.part, nw.ns, it & 1, s));
-    HIPCHK(launch_nt_dir(rows, nw.mask, nw.mi, nw.z, nw.p, nw.Vf, nw.part, nw.ns, it & 1, s));
-    const int slot = it & 1;
-    HIPCHK(hipMemcpyAsync(&nw.flag_h[slot], &nw.ns->cg_done, sizeof(int), hipMemcpyDeviceToHost, s));
+  int it = 0;
+  for (int k = 0; it < cg_max; ++k) {
+    const int slot = k & 1;
+    if (cg_max - it >= kCgGraphIters) {
+      HIPCHK(hipGraphLaunch(cg_graph(pb, pv, I, nw, rows, slot), s));
+      it += kCgGraphIters;
+    } else {
+      for (; it < cg_max; ++it) enqueue_cg_iter(pv, I, nw, rows, it & 1, slot, s);
+    }
     HIPCHK(hipEventRecord(nw.ev[slot], s));
-    if (it >= 1) {
+    if (k >= 1) {
       HIPCHK(hipEventSynchronize(nw.ev[slot ^ 1]));
       if (nw.flag_h[slot ^ 1]) break;
     }
@@ -839,7 +899,7 @@ void newton_run(pdt_problem_s* pb, Instance& I, const pdt_newton_opts& o, Newton
       break;
     }
     const double eps = std::min(o.eps_cap > 0.0 ? o.eps_cap : 1e-9, std::sqrt(m.out[1]));
-    out.cg += nt_direction(pv, I, nw, rows, X, eps, o.cg_rtol, o.cg_max, s);
+    out.cg += nt_direction(pb, pv, I, nw, rows, X, eps, o.cg_rtol, o.cg_max, s);
     double slope = nt_slope(I, nw, rows, X, s);
     if (slope >= 0.0) {
       HIPCHK(launch_nt_negrad(rows, nw.G, nw.mi, nw.Dir, s));
@@ -1163,7 +1223,7 @@ pdt_status pdt_hessian_apply(pdt_problem_t pb, const double* V, double* HV) {
     NewtonWork& nw = ensure_newton(pb, I);
     const ProbView pv = view_var(I, VAR_FP64);
     to_padded(I, V, nw.Vf, s);
-    nt_hessian(pv, I, nw, nw.Vf, nw.Gh, s);
+    nt_hessian(pv, I, nw, nw.Vf, nw.Gh, nullptr, s);
     from_padded(I, nw.Gh, HV, s);
     HIPCHK(hipStreamSynchronize(s));
     g_last_error.clear();
@@ -1191,7 +1251,7 @@ pdt_status pdt_newton_direction(pdt_problem_t pb, int stage, const double* Pi, d
     nt_eval(pv, I, nw, X, s);
     nt_gradient(pv, I, nw, X, s);
     const NtRows rows{(int)I.M, (int)I.N, (int)I.Npad, stage};
-    const int it = nt_direction(pv, I, nw, rows, X, eps, cg_rtol, cg_max, s);
+    const int it = nt_direction(pb, pv, I, nw, rows, X, eps, cg_rtol, cg_max, s);
     const double sl = nt_slope(I, nw, rows, X, s);
     from_padded(I, nw.Dir, Dir, s);
     if (row_max && stage == 2)

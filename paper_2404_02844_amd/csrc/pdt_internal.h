@@ -91,6 +91,8 @@ struct Bufs {
                                  // transposed product, read by the forward product)
   double* fx_part = nullptr;     // [tiles * fx_split][16][16 NT] partial tiles (split forward product)
   unsigned* fx_count = nullptr;  // [tiles] finished workgroups per tile, zero between launches
+  const int* skip = nullptr;     // when set and *skip != 0 the launch returns at once (the
+                                 // Hessian products of a conjugate-gradient solve that stopped)
 };
 
 // One instance of a batched launch: its problem view, buffers, state and step; n_dt

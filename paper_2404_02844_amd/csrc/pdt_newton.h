@@ -43,12 +43,13 @@ hipError_t launch_nt_prep(const NtRows& r, const double* X, const double* G, con
 hipError_t launch_nt_q(const NtRows& r, const uint8_t* mask, const int* mi, const double* h, const double* p,
                        const double* Gh, double* q, double* part, NewtonState* ns, hipStream_t s);
 // part: [4 kNtBlocks] (p'q partials first, r'r and r'z partials from 2 kNtBlocks on);
-// par = CG iteration % 2
+// par = CG iteration % 2; flag: device address of a host-mapped int that the direction
+// kernel sets to 1 once the solve has stopped, else 0
 hipError_t launch_nt_update(const NtRows& r, const uint8_t* mask, const double* h, double* Dir, double* res,
                             double* z, const double* p, const double* q, double* part, NewtonState* ns, int par,
                             hipStream_t s);
 hipError_t launch_nt_dir(const NtRows& r, const uint8_t* mask, const int* mi, const double* z, double* p,
-                         double* Vf, double* part, NewtonState* ns, int par, hipStream_t s);
+                         double* Vf, double* part, NewtonState* ns, int par, int* flag, hipStream_t s);
 hipError_t launch_nt_slope(const NtRows& r, const double* X, const double* Dir, const double* G, const int* mi,
                            double* part, NewtonState* ns, hipStream_t s);
 hipError_t launch_nt_negrad(const NtRows& r, const double* G, const int* mi, double* Dir, hipStream_t s);

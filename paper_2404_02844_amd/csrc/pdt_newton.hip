@@ -82,18 +82,19 @@ __device__ __forceinline__ void block_partials(double (&acc)[K], double* part, i
   }
 }
 
-// fixed-order sum of nb block partials by one block of 256 threads
+// fixed-order sum of nb block partials by one block of 256 threads: strided per-thread
+// sums, an xor butterfly per wave (every lane, and every block given the same partials,
+// ends with the same bits), then the wave sums in wave order
 __device__ __forceinline__ double sum_partials(const double* part, int nb) {
-  __shared__ double sh[256];
+  __shared__ double sh[kWavesPerBlock];
   double s = 0.0;
   for (int k = threadIdx.x; k < nb; k += 256) s += part[k];
-  sh[threadIdx.x] = s;
+  s = group_sum<64>(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
   __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double r = sh[0];
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < kWavesPerBlock; ++w) r += sh[w];
   __syncthreads();
   return r;
 }
@@ -292,18 +293,28 @@ __global__ __launch_bounds__(256) void nt_update_kernel(NtRows r, const uint8_t*
 
 // Next search direction: every block forms r'r and r'z from the update's partials in the
 // same fixed order and takes the same stopping decision and beta = r'z_new / r'z; block 0
-// records r'z_new in rz[par ^ 1] (rz[par] stays readable for the other blocks).
+// records r'z_new in rz[par ^ 1] (rz[par] stays readable for the other blocks) and stores
+// the solve's completion state in *flag (host memory mapped for the device).
 template <int V>
 __global__ __launch_bounds__(256) void nt_dir_kernel(NtRows r, const uint8_t* mask, const int* mi_in, const double* z,
                                                      double* p, double* Vf, const double* part, NewtonState* ns,
-                                                     int par) {
-  if (ns->cg_done) return;
+                                                     int par, int* flag) {
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (ns->cg_done) {
+    if (lead) {
+      *flag = 1;
+      __threadfence_system();
+    }
+    return;
+  }
   const double rr = sum_partials(part, gridDim.x);
   const double rzn = sum_partials(part + gridDim.x, gridDim.x);
   const bool stop = sqrt(rr) <= ns->rtol * ns->nr0 || ns->cg_iter >= ns->cg_max;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (lead) {
     if (stop) ns->cg_done = 1;
     else ns->rz[par ^ 1] = rzn;
+    *flag = stop ? 1 : 0;
+    __threadfence_system();
   }
   if (stop) return;
   const double beta = rzn / ns->rz[par];
@@ -551,11 +562,12 @@ hipError_t launch_nt_update(const NtRows& r, const uint8_t* mask, const double* 
 }
 
 hipError_t launch_nt_dir(const NtRows& r, const uint8_t* mask, const int* mi, const double* z, double* p,
-                         double* Vf, double* part, NewtonState* ns, int par, hipStream_t s) {
+                         double* Vf, double* part, NewtonState* ns, int par, int* flag, hipStream_t s) {
+  if (!flag) return hipErrorInvalidValue;
   const int nb = nt_blocks(r);
 #define K_(V)                                                                                                    \
   hipLaunchKernelGGL((nt_dir_kernel<V>), dim3(nb), dim3(256), 0, s, r, mask, mi, z, p, Vf, part + 2 * kNtBlocks, \
-                     ns, par)
+                     ns, par, flag)
   NT_V_SWITCH(r, K_)
 #undef K_
   return hipGetLastError();

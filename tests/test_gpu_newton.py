@@ -144,6 +144,36 @@ def test_direction_matches_oracle(dev, which, stage):
     pb.close()
 
 
+@pytest.mark.parametrize("cg_max", [1, 3, 4, 5, 7, 8, 9])
+def test_direction_across_graph_boundaries(dev, cg_max):
+    """CG iterations go out four per recorded graph and the remainder one by one; every
+    split of cg_max gives the oracle's iteration count and direction."""
+    inst, F, pb = setup("small")
+    print(f"[newton] direction small stage 1 cg_max={cg_max}", flush=True)
+    X = random_point(inst, 31)
+    ref = oracle_direction(inst, F, X, 1, cg_max)
+    D, _, r = gpu_direction(pb, inst, X, 1, ref["eps"], cg_max, dev)
+    assert r["cg_iters"] == ref["it"]
+    assert np.max(np.abs(D - ref["D"])) <= 1e-9 * np.max(np.abs(ref["D"]))
+    pb.close()
+
+
+def test_hessian_after_a_finished_solve(dev):
+    """A conjugate-gradient solve ends with its stop flag set, which its own Hessian
+    products skip on; a later plain Hessian product must still be computed."""
+    inst, F, pb = setup("small")
+    print("[newton] hessian after direction", flush=True)
+    X = random_point(inst, 41)
+    ref = oracle_direction(inst, F, X, 2, 6)
+    gpu_direction(pb, inst, X, 2, ref["eps"], 6, dev)
+    V = np.random.default_rng(5).normal(size=(inst.M, inst.N))
+    HV = torch.empty((inst.M, inst.N), dtype=torch.float64, device=dev)
+    pb.hessian(gpu(V, dev), HV)
+    ref_hv = fista.hessian_apply(F, inst.gamma, V)
+    assert np.max(np.abs(HV.cpu().numpy() - ref_hv)) <= 1e-12 * np.max(np.abs(ref_hv))
+    pb.close()
+
+
 @pytest.mark.parametrize("stage", [1, 2])
 @pytest.mark.parametrize("which", ["c1", "small", "wide", "gamma0"])
 def test_full_cg_direction_properties(dev, which, stage):

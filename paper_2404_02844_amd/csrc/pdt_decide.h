@@ -21,6 +21,26 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
   return sh[0];
 }
 
+// p[tid] + p[tid + 256] + ... over the indices below n, added in that order from 0.0.
+// The loads of up to 8 terms go out before their additions: a plain loop waits for each
+// load in turn, and these partials come from HBM (written by another kernel).
+__device__ __forceinline__ double strided_sum256(const double* p, int n, int tid) {
+  constexpr int U = 8;
+  double s = 0.0;
+  for (int k0 = tid; k0 < n; k0 += U * 256) {
+    double v[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int k = k0 + j * 256;
+      v[j] = k < n ? p[k] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+      if (k0 + j * 256 < n) s += v[j];
+  }
+  return s;
+}
+
 // The same sum over the values of the first 256 threads of a block of BS >= 256 threads
 // (the others only join the barriers), so every block size adds in one order.
 template <int BS>
@@ -42,9 +62,7 @@ __device__ __forceinline__ void decide_body(const double* partials, int n, Solve
                                             int mode) {
   __shared__ double sh[256];
   if ((mode == DEC_ITER || mode == DEC_RESYNC) && st->done) return;
-  double s = 0.0;
-  if (threadIdx.x < 256)
-    for (int k = threadIdx.x; k < n; k += 256) s += partials[k];
+  const double s = threadIdx.x < 256 ? strided_sum256(partials, n, threadIdx.x) : 0.0;
   const double f = first256_sum<BS>(s, sh);
   if (threadIdx.x != 0) return;
   if (mode == DEC_EVAL) {

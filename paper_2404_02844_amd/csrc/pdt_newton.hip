@@ -12,6 +12,7 @@
 #include <climits>
 #include <cmath>
 
+#include "pdt_decide.h"
 #include "pdt_device.h"
 #include "pdt_newton.h"
 
@@ -87,8 +88,7 @@ __device__ __forceinline__ void block_partials(double (&acc)[K], double* part, i
 // ends with the same bits), then the wave sums in wave order
 __device__ __forceinline__ double sum_partials(const double* part, int nb) {
   __shared__ double sh[kWavesPerBlock];
-  double s = 0.0;
-  for (int k = threadIdx.x; k < nb; k += 256) s += part[k];
+  double s = strided_sum256(part, nb, threadIdx.x);
   s = group_sum<64>(s);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
   __syncthreads();

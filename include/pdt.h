@@ -256,6 +256,12 @@ pdt_status pdt_problem_fx_split(pdt_problem_t problem, int64_t instance, int* sp
  * comparison test of pdt_solve).  Returns PDT_ERR_NOT_CONVERGED (with Pi and info
  * filled) when the method stopped (max_newton reached, or no stage-2 trial accepted)
  * before either test held.
+ * The first Newton call on a problem (this one, pdt_hessian_apply or
+ * pdt_newton_direction) allocates the method's work arrays (eight [M*N] and four [D*N]
+ * FP64 arrays, N padded to a multiple of 16, and a byte mask), two ints of pinned host memory mapped for the device (the CG
+ * completion flags) and, on the first CG solve of each stage, two recorded graphs of
+ * four CG iterations.  The problem keeps all of them until pdt_destroy_problem;
+ * pdt_problem_set_tiles and pdt_problem_set_fx_split drop the graphs.
  */
 typedef struct {
   int64_t max_newton;     /* Newton steps of both stages, >= 0 */

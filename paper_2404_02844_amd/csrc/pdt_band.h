@@ -425,7 +425,9 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
       if (NPASS == 1 || nt0 + k < NT) dst[k] = (TC)R[base + 16u * (nt0 + k)];
   };
   const int nchunks = dhi >= dlo ? (dhi - dlo) / kChunkD + 1 : 0;
-  const int rounds = (nchunks + KS - 1) / KS;
+  // wave wv takes chunks wv, wv + KS, ...: its rounds end with its last nonempty chunk
+  // (chunks past dhi would only add exact zeros)
+  const int rounds = wv < nchunks ? (nchunks - wv + KS - 1) / KS : 0;
   constexpr int stride = kChunkD * KS;
   // the tile's 16 photon numbers are shared by every probe: 1/(m+1) once per workgroup
   double inv[16];

@@ -7,7 +7,8 @@
 // that a difference keeps the accuracy of the window sum itself rather than of the
 // prefix sums, whose magnitude reaches the column sum (~1e4 for a million rows):
 //   1. per block of kRowsPerBlk rows, its compensated column sums;
-//   2. an exclusive compensated scan of those block sums down each column;
+//   2. an exclusive compensated scan of those block sums down each column (a wave per
+//      column, 64 blocks per step);
 //   3. the in-block prefixes, written as (S_hi, S_lo) (M + 1 rows);
 //   4. every output row from two rows of S.
 // Each pass streams the [M][N] array once (HBM-bound).  Step 4 reads only S and its own
@@ -44,16 +45,47 @@ __global__ __launch_bounds__(256) void smooth_blocksum_kernel(const double* Pi, 
   Bl[b * N + n] = lo;
 }
 
+// (hi, lo) += (h2, l2): one compensated pair added to another
+__device__ __forceinline__ void pair_add(double& hi, double& lo, double h2, double l2) {
+  comp_add(hi, lo, h2);
+  lo += l2;
+}
+
+// Exclusive compensated scan of the block sums down each column, one wave per column:
+// 64 blocks per step, scanned across the lanes (Hillis-Steele, earlier blocks added to
+// later ones), on top of the carry of the steps before.
 __global__ __launch_bounds__(256) void smooth_scan_kernel(double* Bh, double* Bl, long long nblk, int N) {
-  const int n = blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int n = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (n >= N) return;
-  double hi = 0.0, lo = 0.0;
-  for (long long b = 0; b < nblk; ++b) {
-    const double vh = Bh[b * N + n], vl = Bl[b * N + n];
-    Bh[b * N + n] = hi;
-    Bl[b * N + n] = lo;
-    comp_add(hi, lo, vh);
-    lo += vl;
+  double ch = 0.0, cl = 0.0;  // sum of the blocks before this step
+  for (long long b0 = 0; b0 < nblk; b0 += 64) {
+    const long long b = b0 + lane;
+    double ih = 0.0, il = 0.0;
+    if (b < nblk) {
+      ih = Bh[b * N + n];
+      il = Bl[b * N + n];
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double oh = __shfl_up(ih, off, 64), ol = __shfl_up(il, off, 64);
+      if (lane >= off) {
+        double h = oh, l = ol;
+        pair_add(h, l, ih, il);
+        ih = h;
+        il = l;
+      }
+    }
+    // exclusive prefix of this lane's block within the step, then the carry
+    double eh = __shfl_up(ih, 1, 64), el = __shfl_up(il, 1, 64);
+    if (lane == 0) eh = el = 0.0;
+    double h = ch, l = cl;
+    pair_add(h, l, eh, el);
+    if (b < nblk) {
+      Bh[b * N + n] = h;
+      Bl[b * N + n] = l;
+    }
+    pair_add(ch, cl, __shfl(ih, 63, 64), __shfl(il, 63, 64));
   }
 }
 
@@ -114,7 +146,7 @@ hipError_t launch_smooth_rows(const double* Pi, double* out, long long M, int N,
   double* Bh = Sl + (M + 1) * N;
   double* Bl = Bh + nblk * N;
   hipLaunchKernelGGL(smooth_blocksum_kernel, dim3(grid_for(nblk * N)), dim3(256), 0, s, Pi, M, N, nblk, Bh, Bl);
-  hipLaunchKernelGGL(smooth_scan_kernel, dim3(grid_for(N)), dim3(256), 0, s, Bh, Bl, nblk, N);
+  hipLaunchKernelGGL(smooth_scan_kernel, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, Bh, Bl, nblk, N);
   hipLaunchKernelGGL(smooth_prefix_kernel, dim3(grid_for(nblk * N)), dim3(256), 0, s, Pi, M, N, nblk, Bh, Bl, Sh,
                      Sl);
   hipLaunchKernelGGL(smooth_apply_kernel, dim3(grid_for(M * N)), dim3(256), 0, s, Pi, Sh, Sl, M, N, divisor, skip,

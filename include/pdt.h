@@ -47,7 +47,10 @@ typedef enum {
 
 typedef enum {
   PDT_FP64 = 0,  /* products and iterates in FP64 (FP64 MFMA) */
-  PDT_FP32 = 1,  /* products and iterates in FP32 (FP32 MFMA), FP64 objective */
+  PDT_FP32 = 1,  /* products and iterates in FP32 (FP32 MFMA), FP64 objective; once a
+                    64-iteration chunk lowers f by < 1e-6 relative (FP32 storage cannot
+                    resolve smaller steps) the solve continues from the promoted iterate in
+                    FP64 (the refinement sweep), unless opts.skip_refine */
   PDT_MIXED = 2  /* FP32 MFMA products on FP64 iterates: F X is kept in FP64 and updated by
                     F (X_new - X_cur) in FP32, resynchronised exactly every 64 iterations;
                     once a 64-iteration chunk lowers f by < 1e-10 relative the solve
@@ -119,28 +122,43 @@ typedef struct {
   double f_star;          /* known optimum value; <= 0 disables the tolerance test */
   double step_L;          /* overrides the Lipschitz constant of the step (L, or L_w with
                              scaling = DIAG); 0 uses the problem's own estimate */
-  double* history;        /* optional device [max_iters]: f after each iteration (FP64) */
+  double* history;        /* optional device [ceil(max_iters / history_stride)]: f after
+                             iteration k for k = 0, stride, 2 stride, ... (FP64) */
   pdt_model_t model;      /* warm-start network for init == PDT_INIT_LEARNED (n_in 258, n_out M) */
   int scaling;            /* pdt_step_scaling */
+  double kkt_tol;         /* > 0: also stop once the KKT residual (see pdt_solve_info.kkt) of
+                             the current iterate is <= kkt_tol; it is formed on the device
+                             every 64 iterations (one gradient product) and needs no f_star */
+  int skip_refine;        /* PDT_FP32 / PDT_MIXED: 0 (default) continue in FP64 once the
+                             reduced-precision phase stalls or meets a tolerance on its own
+                             inexact values; 1 stop at the reduced-precision result */
+  int64_t history_stride; /* spacing of the history entries (0 or 1: every iteration) */
 } pdt_solve_opts;
 
 typedef struct {
   int64_t iters;          /* iterations performed */
   int64_t rejects;        /* candidate steps rejected (momentum restarts) */
   double objective;       /* f at the returned Pi, FP64 */
-  double kkt;             /* KKT residual of App. B with lambda_i = -min_n df/dPi[i][n] */
+  double kkt;             /* KKT residual of App. B at the returned Pi, FP64:
+                             sqrt(mean_{i,n} (Pi[i][n] (g[i][n] + lambda_i))^2), g = grad f,
+                             lambda_i = -min_n g[i][n] */
   double L_used;          /* Lipschitz constant used for the step (L_w with scaling = DIAG) */
   double seconds;         /* wall time of the call */
-  int converged;          /* 1 if the tolerance test was met */
-  int64_t refine_iters;   /* PDT_MIXED: iterations of the FP64 refinement (included in iters) */
+  int converged;          /* 1 if a requested test holds at the returned Pi, evaluated in FP64
+                             (f - f_star <= rel_obj_tol f_star, or kkt <= kkt_tol) */
+  int64_t refine_iters;   /* PDT_FP32 / PDT_MIXED: iterations of the FP64 refinement
+                             (included in iters) */
   int fell_back_to_cold;  /* PDT_INIT_LEARNED: 1 if the predicted start was rejected for 1/N */
+  double fw_gap;          /* Frank-Wolfe gap sum_i (<g_i, Pi_i> - min_n g[i][n]) at the returned
+                             Pi: an upper bound on f - f* (the objective is convex) */
+  int status;             /* pdt_status of this instance (batches: per instance) */
 } pdt_solve_info;
 
 /*
  * Solves instance 0.  Pi: device [M*N] row-major FP64; read when init == USER, always
  * overwritten with the final iterate (rows on the simplex).  Returns
  * PDT_ERR_NOT_CONVERGED (with Pi and info filled) when a tolerance was requested and
- * max_iters ran out first.
+ * did not hold at the returned Pi (evaluated in FP64) when max_iters ran out.
  */
 pdt_status pdt_solve(pdt_problem_t problem, double* Pi, const pdt_solve_opts* opts,
                      pdt_solve_info* info);
@@ -152,7 +170,10 @@ pdt_status pdt_solve(pdt_problem_t problem, double* Pi, const pdt_solve_opts* op
  * band work; 64 iterations are captured in one graph and replayed until every instance
  * reports done.  Pi: host array [n_instances] of device pointers, Pi[k] = [M_k * N_k].
  * f_star: host [n_instances] (nullable) per-instance optimum for the tolerance test.
- * info: host [n_instances] (nullable).  precision: PDT_FP64 or PDT_FP32; no history.
+ * info: host [n_instances] (nullable), each with its own status.  precision: PDT_FP64,
+ * or PDT_FP32, whose batch (unless skip_refine) promotes every instance to FP64 once
+ * each has stalled, met its tolerance on FP32 values or used its iterations, and
+ * continues the unconverged ones together in FP64; no history, no kkt_tol.
  * pdt_solve, pdt_objective and pdt_kkt act on instance 0 of such a problem.
  */
 pdt_status pdt_solve_batch(pdt_problem_t problem, double* const* Pi, const pdt_solve_opts* opts,

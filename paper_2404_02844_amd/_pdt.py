@@ -53,13 +53,15 @@ class pdt_problem_desc(ctypes.Structure):
 class pdt_solve_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("init", ctypes.c_int), ("max_iters", ctypes.c_int64),
                 ("rel_obj_tol", ctypes.c_double), ("f_star", ctypes.c_double), ("step_L", ctypes.c_double),
-                ("history", ctypes.c_void_p), ("model", ctypes.c_void_p), ("scaling", ctypes.c_int)]
+                ("history", ctypes.c_void_p), ("model", ctypes.c_void_p), ("scaling", ctypes.c_int),
+                ("kkt_tol", ctypes.c_double), ("skip_refine", ctypes.c_int), ("history_stride", ctypes.c_int64)]
 
 
 class pdt_solve_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("rejects", ctypes.c_int64), ("objective", ctypes.c_double),
                 ("kkt", ctypes.c_double), ("L_used", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("converged", ctypes.c_int), ("refine_iters", ctypes.c_int64), ("fell_back_to_cold", ctypes.c_int)]
+                ("converged", ctypes.c_int), ("refine_iters", ctypes.c_int64), ("fell_back_to_cold", ctypes.c_int),
+                ("fw_gap", ctypes.c_double), ("status", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -201,15 +203,17 @@ def pdt_destroy_problem(handle) -> None:
 
 
 def pdt_solve(handle, Pi, *, precision=PDT_FP64, init=PDT_INIT_UNIFORM, max_iters=1000, rel_obj_tol=0.0,
-              f_star=0.0, step_L=0.0, history=None, model=None, scaling=PDT_STEP_UNIFORM,
-              allow_not_converged=True) -> dict:
+              f_star=0.0, step_L=0.0, history=None, model=None, scaling=PDT_STEP_UNIFORM, kkt_tol=0.0,
+              skip_refine=False, history_stride=1, allow_not_converged=True) -> dict:
     """Solve in place: ``Pi`` is a contiguous float64 [M, N] GPU tensor."""
     if model is not None and init == PDT_INIT_UNIFORM:
         init = PDT_INIT_LEARNED
     o = pdt_solve_opts(precision=precision, init=init, max_iters=int(max_iters), rel_obj_tol=float(rel_obj_tol),
                        f_star=float(f_star), step_L=float(step_L),
                        history=ctypes.c_void_p(history.data_ptr()) if history is not None else None,
-                       model=(model.handle if isinstance(model, Model) else model), scaling=int(scaling))
+                       model=(model.handle if isinstance(model, Model) else model), scaling=int(scaling),
+                       kkt_tol=float(kkt_tol), skip_refine=int(bool(skip_refine)),
+                       history_stride=int(history_stride))
     info = pdt_solve_info()
     st = _check(lib().pdt_solve(handle, ctypes.c_void_p(Pi.data_ptr()), ctypes.byref(o), ctypes.byref(info)),
                 allow=(PDT_ERR_NOT_CONVERGED,) if allow_not_converged else ())
@@ -501,12 +505,14 @@ class BatchProblem:
         self.handle = out
 
     def solve(self, Pis, *, precision=PDT_FP64, init=PDT_INIT_UNIFORM, max_iters=1000, rel_obj_tol=0.0,
-              f_star=None, step_L=0.0, scaling=PDT_STEP_UNIFORM):
+              f_star=None, step_L=0.0, scaling=PDT_STEP_UNIFORM, skip_refine=False):
+        """Every instance's dict carries its own "status"; the call's own is "batch_status"."""
         import numpy as np
         n = len(self.instances)
         ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() for t in Pis])
         o = pdt_solve_opts(precision=precision, init=init, max_iters=int(max_iters), rel_obj_tol=float(rel_obj_tol),
-                           f_star=0.0, step_L=float(step_L), history=None, model=None, scaling=int(scaling))
+                           f_star=0.0, step_L=float(step_L), history=None, model=None, scaling=int(scaling),
+                           skip_refine=int(bool(skip_refine)))
         fs = None
         if f_star is not None:
             self._fs = np.ascontiguousarray(f_star, dtype=np.float64)
@@ -516,7 +522,7 @@ class BatchProblem:
                     allow=(PDT_ERR_NOT_CONVERGED,))
         out = [i.as_dict() for i in infos]
         for d in out:
-            d["status"] = st
+            d["batch_status"] = st
         return out
 
     def close(self):

@@ -611,6 +611,8 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
       if (mval) b.G[(size_t)m * Npad + n] = g[nt];
     }
     gmin = group_min<16>(gmin);
+    // and the Frank-Wolfe gap partial: sum over the row of x (g - min g)
+    double gap = 0.0;
     if (mval) {
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
@@ -618,17 +620,27 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
         if (n < N) {
           const double e = (double)x[nt] * ((double)g[nt] - (double)gmin);
           part += e * e;
+          gap += e;
         }
       }
     }
     part = group_sum<64>(part);
-    if (lane == 0) red[wv] = part;
+    gap = group_sum<64>(gap);
+    __shared__ double red2[KS];
+    if (lane == 0) {
+      red[wv] = part;
+      red2[wv] = gap;
+    }
     __syncthreads();
     if (tid == 0) {
-      double s = 0.0;
+      double s = 0.0, s2 = 0.0;
 #pragma unroll
-      for (int w = 0; w < KS; ++w) s += red[w];
+      for (int w = 0; w < KS; ++w) {
+        s += red[w];
+        s2 += red2[w];
+      }
       b.partials[mt] = s;
+      b.partials[(M + 15) / 16 + mt] = s2;
     }
   }
 }

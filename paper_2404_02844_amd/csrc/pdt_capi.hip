@@ -145,6 +145,7 @@ struct Instance {
   double graph_step[3] = {0.0, 0.0, 0.0};
   double* graph_hist[3] = {nullptr, nullptr, nullptr};
   const double* graph_w[3] = {nullptr, nullptr, nullptr};
+  bool graph_kkt[3] = {false, false, false};
   // waves per workgroup forced per variant and kernel (0: from the tuning table)
   int ks_force[3][2] = {{0, 0}, {0, 0}, {0, 0}};
   // split contraction of the forward product: workgroups per 16-probe tile
@@ -157,6 +158,10 @@ struct Instance {
 };
 
 }  // namespace
+
+namespace pdt {
+void set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
+}  // namespace pdt
 
 struct pdt_model_s;
 
@@ -179,8 +184,11 @@ struct BatchPlan {
 struct pdt_problem_s {
   hipStream_t stream = nullptr;
   hipStream_t capture = nullptr;  // library-owned stream used only to record graphs
-  BatchPlan plan;
-  Arena plan_arena;
+  BatchPlan plan[2];              // batched launches: [0] FP64, [1] FP32
+  Arena plan_arena[2];
+  SolverState** st_ptrs = nullptr;   // device [n_instances]: every instance's state
+  SolverState* st_gather = nullptr;  // device [n_instances]: their copies, read once per chunk
+  int* st_flags = nullptr;           // device [n_instances]: stop flags set by the host
   int device = 0;
   Arena arena;
   std::vector<Instance> inst;
@@ -470,7 +478,8 @@ void setup_instance(pdt_problem_s* pb, Instance& I, const pdt_problem_desc& d) {
   HIPCHK(hipMemsetAsync(I.fx_count, 0, n_dt * sizeof(unsigned), s));
   set_fx_split(A, I, I.fx_split_auto);
   // room for the partials of any split up to kMaxFxSplit
-  I.n_partials = (int)std::max(n_dt * (kMaxFxSplit + 1), n_mt);
+  // and for the gradient launch's KKT and Frank-Wolfe partials (2 per row tile)
+  I.n_partials = (int)std::max(n_dt * (kMaxFxSplit + 1), 2 * n_mt);
   I.partials = A.alloc<double>(I.n_partials);
   I.st = A.alloc<SolverState>(1);
   I.st_eval = A.alloc<SolverState>(1);
@@ -505,7 +514,8 @@ Work<double>& work_of<double>(Instance& I) { return I.w64; }
 template <>
 Work<float>& work_of<float>(Instance& I) { return I.w32; }
 
-void init_state(hipStream_t s, SolverState* dst, int64_t max_iters, double f_star, double rel_tol) {
+void init_state(hipStream_t s, SolverState* dst, int64_t max_iters, double f_star, double rel_tol,
+                double kkt_tol = 0.0, double mn = 1.0, int64_t hist_stride = 1) {
   SolverState s0;
   std::memset(&s0, 0, sizeof(s0));
   s0.ix_cur = 0;
@@ -515,6 +525,9 @@ void init_state(hipStream_t s, SolverState* dst, int64_t max_iters, double f_sta
   s0.max_iters = max_iters;
   s0.f_star = f_star;
   s0.rel_tol = rel_tol;
+  s0.kkt_tol = kkt_tol;
+  s0.mn = mn;
+  s0.hist_stride = hist_stride > 1 ? hist_stride : 1;
   HIPCHK(hipMemcpyAsync(dst, &s0, sizeof(s0), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
 }
@@ -526,24 +539,48 @@ SolverState read_state(hipStream_t s, const SolverState* src) {
   return h;
 }
 
-// f and (optionally) the gradient of the FP64 iterate already in I.w64.X[0].
-double eval_fp64(pdt_problem_s* pb, Instance& I, bool grad, double* kkt_out) {
+void write_state(hipStream_t s, SolverState* dst, const SolverState& h) {
+  HIPCHK(hipMemcpyAsync(dst, &h, sizeof(h), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+// The state of a refinement that starts over from X[0] of FP64 storage: the counts and
+// targets of the phase before it, no stop, the buffer roles and momentum of a fresh
+// start (the start's forward product reads X[ix_cur], so ix_cur must name X[0]).
+SolverState restart_state(SolverState h) {
+  h.done = 0;
+  h.kkt_hit = 0;
+  h.ix_cur = 0;
+  h.ix_prev = 0;
+  h.ix_new = 1;
+  h.t = 1.0;
+  h.beta = 0.0;
+  h.sel_acc = 0;
+  return h;
+}
+
+// f and (optionally) the gradient of the FP64 iterate already in I.w64.X[0], with the
+// KKT residual and the Frank-Wolfe gap of that iterate (host outputs, nullable).
+double eval_fp64(pdt_problem_s* pb, Instance& I, bool grad, double* kkt_out, double* fw_out = nullptr) {
   hipStream_t s = pb->stream;
   const ProbView pv = view_var(I, VAR_FP64);
   Bufs<double> b = bufs_of(I, I.w64, nullptr);
   init_state(s, I.st_eval, 0, 0.0, 0.0);
   HIPCHK(launch_fx<double>(pv, b, I.st_eval, FX_EVAL, s));
   HIPCHK(launch_decide(I.partials, fx_num_waves(pv), I.st_eval, nullptr, DEC_EVAL, s));
-  if (grad || kkt_out) {
+  if (grad || kkt_out || fw_out) {
+    const int nmt = ftr_num_waves(pv);
     HIPCHK(launch_ftr<double>(pv, b, I.st_eval, FTR_GRAD, 0.0, s));
-    HIPCHK(launch_reduce_sum(I.partials, ftr_num_waves(pv), I.scalar, s));
+    HIPCHK(launch_reduce_sum(I.partials, nmt, I.scalar, s));
+    HIPCHK(launch_reduce_sum(I.partials + nmt, nmt, I.scalar + 1, s));
   }
   SolverState h = read_state(s, I.st_eval);
-  if (kkt_out) {
-    double sum = 0;
-    HIPCHK(hipMemcpyAsync(&sum, I.scalar, sizeof(double), hipMemcpyDeviceToHost, s));
+  if (kkt_out || fw_out) {
+    double sum[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(sum, I.scalar, sizeof(sum), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    *kkt_out = std::sqrt(sum / ((double)I.M * (double)I.N));
+    if (kkt_out) *kkt_out = std::sqrt(sum[0] / ((double)I.M * (double)I.N));
+    if (fw_out) *fw_out = sum[1];
   }
   return h.f_eval;
 }
@@ -560,6 +597,18 @@ void enqueue_iters(const ProbView& pv, const Bufs<TS>& b, SolverState* st, doubl
     HIPCHK((launch_fx<TS, TC>(pv, b, st, delta ? FX_DELTA : FX_ITER, s)));
     HIPCHK(launch_decide(b.partials, nfx, st, b.history, DEC_ITER, s));
   }
+}
+
+// KKT test of the current iterate (every kGraphIters iterations when opts.kkt_tol > 0):
+// its residual F X_cur - P, the gradient product at X_cur with the KKT and Frank-Wolfe
+// partials, then DEC_KKT, which stops the solve once the residual is small enough.
+// pvs is the view of the storage precision (the mixed path's gradient runs in FP64,
+// after the chunk's exact resync).
+template <typename TS>
+void enqueue_kkt(const ProbView& pvs, const Bufs<TS>& b, SolverState* st, hipStream_t s) {
+  HIPCHK(launch_resid_cur<TS>(b, st, (long long)pvs.D * pvs.Npad, s));
+  HIPCHK((launch_ftr<TS, TS>(pvs, b, st, FTR_GRAD, 0.0, s)));
+  HIPCHK(launch_decide(b.partials, ftr_num_waves(pvs), st, nullptr, DEC_KKT, s));
 }
 
 // End of a chunk of the mixed path: exact products of X_prev and X_cur replace the
@@ -588,8 +637,9 @@ void drop_graphs(Instance& I) {
 // products of the previous and current iterates and the exact objective, which remove
 // the drift of those updates.
 template <typename TS, typename TC>
-hipGraphExec_t get_graph(pdt_problem_s* pb, Instance& I, int var, const Bufs<TS>& b, double step) {
-  if (I.graph[var] && I.graph_step[var] == step && I.graph_hist[var] == b.history && I.graph_w[var] == b.wrow)
+hipGraphExec_t get_graph(pdt_problem_s* pb, Instance& I, int var, const Bufs<TS>& b, double step, bool kkt) {
+  if (I.graph[var] && I.graph_step[var] == step && I.graph_hist[var] == b.history && I.graph_w[var] == b.wrow &&
+      I.graph_kkt[var] == kkt)
     return I.graph[var];
   if (I.graph[var]) (void)hipGraphExecDestroy(I.graph[var]);
   I.graph[var] = nullptr;
@@ -604,6 +654,7 @@ hipGraphExec_t get_graph(pdt_problem_s* pb, Instance& I, int var, const Bufs<TS>
   try {
     enqueue_iters<TS, TC>(pv, b, I.st, step, kGraphIters, var == VAR_MIXED, cs);
     if (var == VAR_MIXED) enqueue_resync<TS>(pv64, b, I.st, cs);
+    if (kkt) enqueue_kkt<TS>(var == VAR_MIXED ? pv64 : pv, b, I.st, cs);
   } catch (...) {
     (void)hipStreamEndCapture(cs, &g);
     if (g) (void)hipGraphDestroy(g);
@@ -618,67 +669,114 @@ hipGraphExec_t get_graph(pdt_problem_s* pb, Instance& I, int var, const Bufs<TS>
   I.graph_step[var] = step;
   I.graph_hist[var] = b.history;
   I.graph_w[var] = b.wrow;
+  I.graph_kkt[var] = kkt;
   return ge;
 }
 
 // Runs iterations of one variant from the current device state until it reports done,
-// max_iters is reached, or (stagnate = true) a chunk lowers f by less than 1e-10
-// relative.  Returns the state read after the last chunk.
+// its iterations run out, or (stall > 0) a chunk lowers f by less than stall relative.
+// With kkt, every chunk ends with the KKT test.  Returns the state read after the last
+// chunk.
 template <typename TS, typename TC>
-SolverState run_chunks(pdt_problem_s* pb, Instance& I, int var, const Bufs<TS>& b, double step, int64_t budget,
-                       bool stagnate) {
+SolverState run_chunks(pdt_problem_s* pb, Instance& I, int var, const Bufs<TS>& b, double step, double stall,
+                       bool kkt) {
   hipStream_t s = pb->stream;
   const ProbView pv = view_var(I, var);
   const ProbView pv64 = view_var(I, VAR_FP64);
   SolverState h = read_state(s, I.st);
-  int64_t launched = 0;
-  while (launched < budget && !h.done) {
+  while (!h.done && h.iter < h.max_iters) {
     const double f0 = h.f_cur;
-    if (budget - launched >= kGraphIters) {
-      HIPCHK(hipGraphLaunch(get_graph<TS, TC>(pb, I, var, b, step), s));
-      launched += kGraphIters;
+    const int64_t left = h.max_iters - h.iter;
+    if (left >= kGraphIters) {
+      HIPCHK(hipGraphLaunch(get_graph<TS, TC>(pb, I, var, b, step, kkt), s));
     } else {
-      const int64_t n = budget - launched;
-      enqueue_iters<TS, TC>(pv, b, I.st, step, n, var == VAR_MIXED, s);
+      enqueue_iters<TS, TC>(pv, b, I.st, step, left, var == VAR_MIXED, s);
       if (var == VAR_MIXED) enqueue_resync<TS>(pv64, b, I.st, s);
-      launched += n;
+      if (kkt) enqueue_kkt<TS>(var == VAR_MIXED ? pv64 : pv, b, I.st, s);
     }
     h = read_state(s, I.st);
-    if (stagnate && f0 - h.f_cur <= 1e-10 * h.f_cur) break;
+    if (stall > 0 && f0 - h.f_cur <= stall * h.f_cur) break;
   }
   return h;
 }
 
+// Starts a solve (or a refinement) from X[0] of the storage precision: exact products,
+// f, fresh momentum and the KKT test of the start; iterations carry on from the state.
 template <typename T>
-void run_loop(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double step, const double* wrow, int var,
-              SolverState& out) {
+void start_from_x0(pdt_problem_s* pb, Instance& I, const Bufs<T>& b, int var, bool kkt) {
   hipStream_t s = pb->stream;
   const ProbView pv = view_var(I, var);
-  Work<T>& w = work_of<T>(I);
-  Bufs<T> b = bufs_of(I, w, o.history, wrow);
   HIPCHK(launch_fx<T>(pv, b, I.st, FX_INIT, s));
   HIPCHK(launch_decide(I.partials, fx_num_waves(pv), I.st, nullptr, DEC_INIT, s));
-  out = run_chunks<T, T>(pb, I, var, b, step, o.max_iters, false);
+  if (kkt) enqueue_kkt<T>(pv, b, I.st, s);
 }
 
+// Stall thresholds per 64-iteration chunk: FP32 products on FP64 iterates resolve the
+// objective to ~1e-10 relative after each exact resync; FP32 iterates cannot take steps
+// below their own rounding, which shows as progress under ~1e-6 relative.
+constexpr double kStallMixed = 1e-10;
+constexpr double kStallFp32 = 1e-6;
+
 // Mixed path: FP32 products on FP64 iterates until progress stalls, then the FP64
-// refinement continues from the same state to the requested tolerance.
+// refinement continues from the same state to the requested tolerance.  A stop raised
+// during the FP32-product phase by the objective test compared values built from FP32
+// updates; it is provisional until an exact resync confirms it.
 void run_mixed(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double step, const double* wrow,
                SolverState& out, int64_t& refine_iters) {
   hipStream_t s = pb->stream;
-  const ProbView pv = view_var(I, VAR_FP64);
+  const bool kkt = o.kkt_tol > 0;
   if (!I.w64.dX) {
     const size_t xm = (size_t)I.M * I.Npad;
     I.w64.dX = pb->arena.alloc<float>(xm);
     HIPCHK(hipMemsetAsync(I.w64.dX, 0, xm * sizeof(float), s));
   }
   Bufs<double> b = bufs_of(I, I.w64, o.history, wrow);
-  HIPCHK(launch_fx<double>(pv, b, I.st, FX_INIT, s));
-  HIPCHK(launch_decide(I.partials, fx_num_waves(pv), I.st, nullptr, DEC_INIT, s));
-  SolverState h = run_chunks<double, float>(pb, I, VAR_MIXED, b, step, o.max_iters, true);
+  start_from_x0<double>(pb, I, b, VAR_FP64, kkt);
+  SolverState h = run_chunks<double, float>(pb, I, VAR_MIXED, b, step, kStallMixed, kkt);
   const int64_t mixed_iters = h.iter;
-  if (!h.done) h = run_chunks<double, double>(pb, I, VAR_FP64, b, step, o.max_iters - mixed_iters, false);
+  if (h.done && !h.kkt_hit && h.iter < h.max_iters) {
+    // the objective test held on FP32-updated products: redo it on exact ones
+    h.done = 0;
+    write_state(s, I.st, h);
+    enqueue_resync<double>(view_var(I, VAR_FP64), b, I.st, s);
+    h = read_state(s, I.st);
+  }
+  if (!h.done && !o.skip_refine) h = run_chunks<double, double>(pb, I, VAR_FP64, b, step, 0.0, kkt);
   refine_iters = h.iter - mixed_iters;
+  out = h;
+}
+
+// FP32 path: FP32 iterates and products until progress stalls (or a test holds on FP32
+// values); then, unless skip_refine, the iterate is promoted to FP64 and the FP64 method
+// continues from it with fresh momentum.  The promoted iterate is left in X64[0] either way.
+void run_fp32(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double step, const double* wrow,
+              SolverState& out, int64_t& refine_iters) {
+  hipStream_t s = pb->stream;
+  Arena& A = pb->arena;
+  const size_t Np = (size_t)I.Npad, M = (size_t)I.M;
+  const bool kkt = o.kkt_tol > 0;
+  if (!I.P32) {
+    I.P32 = A.alloc<float>((size_t)I.D * Np);
+    HIPCHK(launch_convert_pad<double, float>(I.P64, I.P32, (long long)I.D, (int)Np, (int)Np, (int)Np, s));
+  }
+  ensure_work<float>(A, I, I.w32, I.P32);
+  HIPCHK(launch_convert_pad<double, float>(I.w64.X[0], I.w32.X[0], (long long)M, (int)Np, (int)Np, (int)Np, s));
+  Bufs<float> b32 = bufs_of(I, I.w32, o.history, wrow);
+  start_from_x0<float>(pb, I, b32, VAR_FP32, kkt);
+  SolverState h = run_chunks<float, float>(pb, I, VAR_FP32, b32, step, o.skip_refine ? 0.0 : kStallFp32, kkt);
+  HIPCHK(launch_convert_pad<float, double>(I.w32.X[h.ix_cur], I.w64.X[0], (long long)M, (int)Np, (int)Np, (int)Np,
+                                           s));
+  const int64_t fp32_iters = h.iter;
+  if (!o.skip_refine && h.iter < h.max_iters) {
+    // every FP32-phase stop is provisional: the FP64 start re-tests it on exact values
+    write_state(s, I.st, restart_state(h));
+    Bufs<double> b64 = bufs_of(I, I.w64, o.history, wrow);
+    start_from_x0<double>(pb, I, b64, VAR_FP64, kkt);
+    h = run_chunks<double, double>(pb, I, VAR_FP64, b64, step, 0.0, kkt);
+    if (h.ix_cur != 0)
+      HIPCHK(hipMemcpyAsync(I.w64.X[0], I.w64.X[h.ix_cur], M * Np * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  refine_iters = h.iter - fp32_iters;
   out = h;
 }
 
@@ -1046,8 +1144,10 @@ void pdt_destroy_problem(pdt_problem_t problem) {
       if (e) (void)hipEventDestroy(e);
     if (I.nw.flag_h) (void)hipHostFree(I.nw.flag_h);
   }
-  if (problem->plan.graph) (void)hipGraphExecDestroy(problem->plan.graph);
-  problem->plan_arena.release();
+  for (int k = 0; k < 2; ++k) {
+    if (problem->plan[k].graph) (void)hipGraphExecDestroy(problem->plan[k].graph);
+    problem->plan_arena[k].release();
+  }
   if (problem->capture) (void)hipStreamDestroy(problem->capture);
   problem->arena.release();
   delete problem;
@@ -1078,9 +1178,11 @@ pdt_status pdt_problem_set_tiles(pdt_problem_t pb, int64_t instance, int precisi
     I.ks_force[precision][0] = ks_fx;
     I.ks_force[precision][1] = ks_ftr;
     drop_graphs(I);
-    if (pb->plan.graph) (void)hipGraphExecDestroy(pb->plan.graph);
-    pb->plan.graph = nullptr;
-    pb->plan.prec = -1;
+    for (BatchPlan& P : pb->plan) {
+      if (P.graph) (void)hipGraphExecDestroy(P.graph);
+      P.graph = nullptr;
+      P.prec = -1;
+    }
     return PDT_OK;
   } catch (...) {
     return status_of_current_exception();
@@ -1277,6 +1379,8 @@ pdt_status pdt_solve(pdt_problem_t pb, double* Pi, const pdt_solve_opts* opts, p
     return set_err(PDT_ERR_INVALID_ARG, "precision not supported");
   if (!std::isfinite(o.rel_obj_tol) || o.rel_obj_tol < 0 || !std::isfinite(o.f_star))
     return set_err(PDT_ERR_INVALID_ARG, "bad tolerance");
+  if (!std::isfinite(o.kkt_tol) || o.kkt_tol < 0) return set_err(PDT_ERR_INVALID_ARG, "kkt_tol must be finite and >= 0");
+  if (o.history_stride < 0) return set_err(PDT_ERR_INVALID_ARG, "history_stride must be >= 0");
   if (o.scaling != PDT_STEP_UNIFORM && o.scaling != PDT_STEP_DIAG) return set_err(PDT_ERR_INVALID_ARG, "bad scaling");
   const auto t0 = std::chrono::steady_clock::now();
   try {
@@ -1300,31 +1404,31 @@ pdt_status pdt_solve(pdt_problem_t pb, double* Pi, const pdt_solve_opts* opts, p
     int fell_back = 0;
     if (o.init == PDT_INIT_LEARNED) fell_back = learned_start(pb, I, o.model);
     const double f_star = o.f_star > 0 ? o.f_star : 0.0;
-    init_state(s, I.st, o.max_iters, f_star, o.rel_obj_tol);
+    init_state(s, I.st, o.max_iters, f_star, o.rel_obj_tol, o.kkt_tol, (double)M * (double)N, o.history_stride);
     SolverState fin;
     int64_t refine_iters = 0;
-    if (o.precision == PDT_FP64 || o.precision == PDT_MIXED) {
-      if (o.precision == PDT_FP64) run_loop<double>(pb, I, o, step, wrow, VAR_FP64, fin);
-      else run_mixed(pb, I, o, step, wrow, fin, refine_iters);
-      if (fin.ix_cur != 0)
-        HIPCHK(hipMemcpyAsync(I.w64.X[0], I.w64.X[fin.ix_cur], M * Np * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (o.precision == PDT_FP64) {
+      Bufs<double> b = bufs_of(I, I.w64, o.history, wrow);
+      start_from_x0<double>(pb, I, b, VAR_FP64, o.kkt_tol > 0);
+      fin = run_chunks<double, double>(pb, I, VAR_FP64, b, step, 0.0, o.kkt_tol > 0);
+    } else if (o.precision == PDT_MIXED) {
+      run_mixed(pb, I, o, step, wrow, fin, refine_iters);
     } else {
-      if (!I.P32) {
-        I.P32 = A.alloc<float>((size_t)I.D * Np);
-        HIPCHK(launch_convert_pad<double, float>(I.P64, I.P32, (long long)I.D, (int)Np, (int)Np, (int)Np, s));
-      }
-      ensure_work<float>(A, I, I.w32, I.P32);
-      HIPCHK(launch_convert_pad<double, float>(I.w64.X[0], I.w32.X[0], (long long)M, (int)Np, (int)Np, (int)Np, s));
-      run_loop<float>(pb, I, o, step, wrow, VAR_FP32, fin);
-      HIPCHK(launch_convert_pad<float, double>(I.w32.X[fin.ix_cur], I.w64.X[0], (long long)M, (int)Np, (int)Np,
-                                               (int)Np, s));
+      run_fp32(pb, I, o, step, wrow, fin, refine_iters);
     }
-    double kkt = 0;
-    const double f = eval_fp64(pb, I, true, &kkt);
+    if (o.precision != PDT_FP32 && fin.ix_cur != 0)
+      HIPCHK(hipMemcpyAsync(I.w64.X[0], I.w64.X[fin.ix_cur], M * Np * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // the tests that decide convergence are re-evaluated in FP64 at the returned iterate
+    double kkt = 0, fw = 0;
+    const double f = eval_fp64(pb, I, true, &kkt, &fw);
     HIPCHK(hipMemcpy2DAsync(Pi, N * sizeof(double), I.w64.X[0], Np * sizeof(double), N * sizeof(double), M,
                             hipMemcpyDeviceToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
-    const bool conv = f_star > 0 && fin.f_cur - f_star <= o.rel_obj_tol * f_star;
+    const bool want_obj = f_star > 0 && o.rel_obj_tol > 0, want_kkt = o.kkt_tol > 0;
+    const bool conv = (want_obj && f - f_star <= o.rel_obj_tol * f_star) || (want_kkt && kkt <= o.kkt_tol);
+    pdt_status st = PDT_OK;
+    if (!std::isfinite(f)) st = set_err(PDT_ERR_NUMERIC, "objective is not finite");
+    else if ((want_obj || want_kkt) && !conv) st = set_err(PDT_ERR_NOT_CONVERGED, "max_iters reached before the tolerance");
     if (info) {
       info->iters = fin.iter;
       info->rejects = fin.rejects;
@@ -1335,12 +1439,11 @@ pdt_status pdt_solve(pdt_problem_t pb, double* Pi, const pdt_solve_opts* opts, p
       info->converged = conv ? 1 : 0;
       info->refine_iters = refine_iters;
       info->fell_back_to_cold = fell_back;
+      info->fw_gap = fw;
+      info->status = st;
     }
-    if (!std::isfinite(f)) return set_err(PDT_ERR_NUMERIC, "objective is not finite");
-    if (f_star > 0 && o.rel_obj_tol > 0 && !conv)
-      return set_err(PDT_ERR_NOT_CONVERGED, "max_iters reached before the tolerance");
-    g_last_error.clear();
-    return PDT_OK;
+    if (st == PDT_OK) g_last_error.clear();
+    return st;
   } catch (...) {
     return status_of_current_exception();
   }
@@ -1708,12 +1811,17 @@ int learned_start(pdt_problem_s* pb, Instance& I, pdt_model_s* md) {
 namespace {
 
 template <typename T>
-void build_plan(pdt_problem_s* pb, int prec, int scaling, const std::vector<double>& steps) {
-  BatchPlan& P = pb->plan;
+constexpr int plan_slot() { return std::is_same<T, float>::value ? 1 : 0; }
+
+template <typename T>
+void build_plan(pdt_problem_s* pb, int scaling, const std::vector<double>& steps) {
+  const int prec = std::is_same<T, float>::value ? PDT_FP32 : PDT_FP64;
+  BatchPlan& P = pb->plan[plan_slot<T>()];
+  Arena& PA = pb->plan_arena[plan_slot<T>()];
   if (P.prec == prec && P.scaling == scaling && P.steps == steps) return;
   if (P.graph) (void)hipGraphExecDestroy(P.graph);
   P = BatchPlan();
-  pb->plan_arena.release();
+  PA.release();
   hipStream_t s = pb->stream;
   const size_t n = pb->inst.size();
   const int var = prec == PDT_FP32 ? VAR_FP32 : VAR_FP64;
@@ -1749,7 +1857,7 @@ void build_plan(pdt_problem_s* pb, int prec, int scaling, const std::vector<doub
     }
     for (int t = 0; t < bi.n_mt; ++t) ftr[kftr].push_back({(int64_t)nt, int2{(int)k, t}});
   }
-  P.insts = pb->plan_arena.alloc<BatchInst<T>>(n);
+  P.insts = PA.alloc<BatchInst<T>>(n);
   HIPCHK(hipMemcpyAsync(P.insts, host.data(), n * sizeof(BatchInst<T>), hipMemcpyHostToDevice, s));
   auto by_cost = [](const std::pair<int64_t, int2>& a, const std::pair<int64_t, int2>& b) {
     return a.first > b.first;
@@ -1763,7 +1871,7 @@ void build_plan(pdt_problem_s* pb, int prec, int scaling, const std::vector<doub
     L.nt = c / 2;
     L.ks = (c & 1) ? 8 : 4;
     L.n = (int)items.size();
-    L.items = pb->plan_arena.alloc<int2>(items.size());
+    L.items = PA.alloc<int2>(items.size());
     HIPCHK(hipMemcpyAsync(L.items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice, s));
     out.push_back(L);
   };
@@ -1779,7 +1887,7 @@ void build_plan(pdt_problem_s* pb, int prec, int scaling, const std::vector<doub
 
 template <typename T>
 void enqueue_batch_iters(pdt_problem_s* pb, int64_t iters, hipStream_t s) {
-  BatchPlan& P = pb->plan;
+  BatchPlan& P = pb->plan[plan_slot<T>()];
   const BatchInst<T>* insts = static_cast<const BatchInst<T>*>(P.insts);
   const int n = (int)pb->inst.size();
   for (int64_t k = 0; k < iters; ++k) {
@@ -1790,48 +1898,72 @@ void enqueue_batch_iters(pdt_problem_s* pb, int64_t iters, hipStream_t s) {
   }
 }
 
-template <typename T>
-void run_batch(pdt_problem_s* pb, const pdt_solve_opts& o, int prec, std::vector<SolverState>& out) {
+// Every instance's state, with one gather launch and one copy.
+void read_batch_states(pdt_problem_s* pb, std::vector<SolverState>& out) {
   hipStream_t s = pb->stream;
-  BatchPlan& P = pb->plan;
+  const int n = (int)pb->inst.size();
+  out.resize(n);
+  HIPCHK(launch_gather_states(pb->st_ptrs, n, pb->st_gather, s));
+  HIPCHK(hipMemcpyAsync(out.data(), pb->st_gather, n * sizeof(SolverState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+// One phase of a batch from X[0] of every instance (storage T): exact products, f and
+// fresh momentum, then chunks of kGraphIters iterations (one recorded graph) until every
+// instance is done.  With stall > 0 an instance whose chunk lowered f by less than stall
+// relative is stopped (its reduced-precision phase is over).
+template <typename T>
+void run_batch(pdt_problem_s* pb, double stall, std::vector<SolverState>& out) {
+  hipStream_t s = pb->stream;
+  BatchPlan& P = pb->plan[plan_slot<T>()];
   const BatchInst<T>* insts = static_cast<const BatchInst<T>*>(P.insts);
   const int n = (int)pb->inst.size();
   for (const LaunchList& L : P.fx) HIPCHK((launch_fx_batch<T, T>(L.nt, L.ks, insts, L.items, L.n, FX_INIT, s)));
   HIPCHK(launch_decide_batch<T>(insts, n, DEC_INIT, s));
-  if (o.max_iters >= kGraphIters && !P.graph) {
-    if (!pb->capture) HIPCHK(hipStreamCreateWithFlags(&pb->capture, hipStreamNonBlocking));
-    hipGraph_t g = nullptr;
-    HIPCHK(hipStreamBeginCapture(pb->capture, hipStreamCaptureModeThreadLocal));
-    try {
-      enqueue_batch_iters<T>(pb, kGraphIters, pb->capture);
-    } catch (...) {
-      (void)hipStreamEndCapture(pb->capture, &g);
-      if (g) (void)hipGraphDestroy(g);
-      throw;
-    }
-    HIPCHK(hipStreamEndCapture(pb->capture, &g));
-    hipError_t e = hipGraphInstantiate(&P.graph, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    HIPCHK(e);
-  }
-  std::vector<SolverState> st(n);
-  int64_t launched = 0;
-  while (launched < o.max_iters) {
-    if (o.max_iters - launched >= kGraphIters) {
+  std::vector<SolverState> st;
+  read_batch_states(pb, st);
+  std::vector<int> flags(n, 0);
+  for (;;) {
+    int64_t left = 0;
+    for (int k = 0; k < n; ++k)
+      if (!st[k].done) left = std::max<int64_t>(left, st[k].max_iters - st[k].iter);
+    if (left <= 0) break;
+    if (left >= kGraphIters) {
+      if (!P.graph) {
+        if (!pb->capture) HIPCHK(hipStreamCreateWithFlags(&pb->capture, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(pb->capture, hipStreamCaptureModeThreadLocal));
+        try {
+          enqueue_batch_iters<T>(pb, kGraphIters, pb->capture);
+        } catch (...) {
+          (void)hipStreamEndCapture(pb->capture, &g);
+          if (g) (void)hipGraphDestroy(g);
+          throw;
+        }
+        HIPCHK(hipStreamEndCapture(pb->capture, &g));
+        hipError_t e = hipGraphInstantiate(&P.graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(e);
+      }
       HIPCHK(hipGraphLaunch(P.graph, s));
-      launched += kGraphIters;
     } else {
-      enqueue_batch_iters<T>(pb, o.max_iters - launched, s);
-      launched = o.max_iters;
+      enqueue_batch_iters<T>(pb, left, s);
     }
-    bool all = true;
-    for (int k = 0; k < n; ++k) {
-      st[k] = read_state(s, pb->inst[k].st);
-      all = all && st[k].done;
+    std::vector<SolverState> prev = st;
+    read_batch_states(pb, st);
+    if (stall > 0) {
+      bool any = false;
+      for (int k = 0; k < n; ++k) {
+        flags[k] = !st[k].done && prev[k].f_cur - st[k].f_cur <= stall * st[k].f_cur;
+        any = any || flags[k];
+      }
+      if (any) {
+        HIPCHK(hipMemcpyAsync(pb->st_flags, flags.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+        HIPCHK(launch_mark_done(pb->st_ptrs, pb->st_flags, n, s));
+        read_batch_states(pb, st);
+      }
     }
-    if (all) break;
   }
-  for (int k = 0; k < n; ++k) st[k] = read_state(s, pb->inst[k].st);
   out = st;
 }
 
@@ -1849,6 +1981,7 @@ pdt_status pdt_solve_batch(pdt_problem_t pb, double* const* Pi, const pdt_solve_
   if (o.precision != PDT_FP64 && o.precision != PDT_FP32) return set_err(PDT_ERR_INVALID_ARG, "batch precision must be FP64 or FP32");
   if (o.init != PDT_INIT_UNIFORM && o.init != PDT_INIT_USER) return set_err(PDT_ERR_INVALID_ARG, "bad init");
   if (o.history) return set_err(PDT_ERR_INVALID_ARG, "history is not supported for batches");
+  if (o.kkt_tol != 0.0) return set_err(PDT_ERR_INVALID_ARG, "kkt_tol is not supported for batches");
   if (o.scaling != PDT_STEP_UNIFORM && o.scaling != PDT_STEP_DIAG) return set_err(PDT_ERR_INVALID_ARG, "bad scaling");
   for (size_t k = 0; k < n; ++k)
     if (!Pi[k]) return set_err(PDT_ERR_INVALID_ARG, "Pi[k] must not be NULL");
@@ -1856,6 +1989,14 @@ pdt_status pdt_solve_batch(pdt_problem_t pb, double* const* Pi, const pdt_solve_
   try {
     hipStream_t s = pb->stream;
     Arena& A = pb->arena;
+    if (!pb->st_ptrs) {
+      std::vector<SolverState*> ptrs(n);
+      for (size_t k = 0; k < n; ++k) ptrs[k] = pb->inst[k].st;
+      pb->st_ptrs = A.alloc<SolverState*>(n);
+      pb->st_gather = A.alloc<SolverState>(n);
+      pb->st_flags = A.alloc<int>(n);
+      HIPCHK(hipMemcpyAsync(pb->st_ptrs, ptrs.data(), n * sizeof(SolverState*), hipMemcpyHostToDevice, s));
+    }
     std::vector<double> steps(n), Ls(n);
     for (size_t k = 0; k < n; ++k) {
       Instance& I = pb->inst[k];
@@ -1866,7 +2007,7 @@ pdt_status pdt_solve_batch(pdt_problem_t pb, double* const* Pi, const pdt_solve_
       if (o.init == PDT_INIT_USER) HIPCHK(launch_project_rows<double>(Pi[k], I.w64.X[0], (long long)M, (int)N, (int)N, (int)Np, s));
       else HIPCHK(launch_fill_rows<double>(I.w64.X[0], (long long)M, (int)N, (int)Np, 1.0 / (double)N, s));
       const double fs = (f_star && f_star[k] > 0) ? f_star[k] : 0.0;
-      init_state(s, I.st, o.max_iters, fs, o.rel_obj_tol);
+      init_state(s, I.st, o.max_iters, fs, o.rel_obj_tol, 0.0, (double)M * (double)N, 1);
       if (o.precision == PDT_FP32) {
         if (!I.P32) {
           I.P32 = A.alloc<float>((size_t)I.D * Np);
@@ -1876,33 +2017,54 @@ pdt_status pdt_solve_batch(pdt_problem_t pb, double* const* Pi, const pdt_solve_
         HIPCHK(launch_convert_pad<double, float>(I.w64.X[0], I.w32.X[0], (long long)M, (int)Np, (int)Np, (int)Np, s));
       }
     }
-    std::vector<SolverState> fin;
+    std::vector<SolverState> fin, fin32;
+    bool refined = false;
     if (o.precision == PDT_FP64) {
-      build_plan<double>(pb, PDT_FP64, o.scaling, steps);
-      run_batch<double>(pb, o, PDT_FP64, fin);
+      build_plan<double>(pb, o.scaling, steps);
+      run_batch<double>(pb, 0.0, fin);
     } else {
-      build_plan<float>(pb, PDT_FP32, o.scaling, steps);
-      run_batch<float>(pb, o, PDT_FP32, fin);
+      build_plan<float>(pb, o.scaling, steps);
+      run_batch<float>(pb, o.skip_refine ? 0.0 : kStallFp32, fin32);
+      // the promoted FP32 iterates, in X64[0]
+      for (size_t k = 0; k < n; ++k) {
+        Instance& I = pb->inst[k];
+        const size_t Np = (size_t)I.Npad;
+        HIPCHK(launch_convert_pad<float, double>(I.w32.X[fin32[k].ix_cur], I.w64.X[0], (long long)I.M, (int)Np,
+                                                 (int)Np, (int)Np, s));
+      }
+      fin = fin32;
+      if (!o.skip_refine) {
+        // FP64 refinement of every instance together: each starts from its promoted
+        // iterate with fresh momentum and its remaining iterations; an instance whose
+        // exact objective already meets its tolerance (or that has none left) stops at once
+        std::vector<SolverState> restart(n);
+        for (size_t k = 0; k < n; ++k) {
+          restart[k] = restart_state(fin32[k]);
+          HIPCHK(hipMemcpyAsync(pb->inst[k].st, &restart[k], sizeof(SolverState), hipMemcpyHostToDevice, s));
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        build_plan<double>(pb, o.scaling, steps);
+        run_batch<double>(pb, 0.0, fin);
+        refined = true;
+      }
     }
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    bool all_conv = true;
+    bool all_conv = true, all_finite = true;
     for (size_t k = 0; k < n; ++k) {
       Instance& I = pb->inst[k];
       const size_t Np = (size_t)I.Npad, N = (size_t)I.N, M = (size_t)I.M;
-      if (o.precision == PDT_FP64) {
-        if (fin[k].ix_cur != 0)
-          HIPCHK(hipMemcpyAsync(I.w64.X[0], I.w64.X[fin[k].ix_cur], M * Np * sizeof(double), hipMemcpyDeviceToDevice, s));
-      } else {
-        HIPCHK(launch_convert_pad<float, double>(I.w32.X[fin[k].ix_cur], I.w64.X[0], (long long)M, (int)Np, (int)Np,
-                                                 (int)Np, s));
-      }
-      double kkt = 0;
-      const double f = eval_fp64(pb, I, true, &kkt);
+      if ((o.precision == PDT_FP64 || refined) && fin[k].ix_cur != 0)
+        HIPCHK(hipMemcpyAsync(I.w64.X[0], I.w64.X[fin[k].ix_cur], M * Np * sizeof(double), hipMemcpyDeviceToDevice, s));
+      double kkt = 0, fw = 0;
+      const double f = eval_fp64(pb, I, true, &kkt, &fw);
       HIPCHK(hipMemcpy2DAsync(Pi[k], N * sizeof(double), I.w64.X[0], Np * sizeof(double), N * sizeof(double), M,
                               hipMemcpyDeviceToDevice, s));
       const double fs = (f_star && f_star[k] > 0) ? f_star[k] : 0.0;
-      const bool conv = fs > 0 && fin[k].f_cur - fs <= o.rel_obj_tol * fs;
-      all_conv = all_conv && (conv || fs <= 0 || o.rel_obj_tol <= 0);
+      const bool want = fs > 0 && o.rel_obj_tol > 0;
+      const bool conv = want && f - fs <= o.rel_obj_tol * fs;
+      const int stk = !std::isfinite(f) ? PDT_ERR_NUMERIC : (want && !conv ? PDT_ERR_NOT_CONVERGED : PDT_OK);
+      all_conv = all_conv && (conv || !want);
+      all_finite = all_finite && std::isfinite(f);
       if (info) {
         info[k].iters = fin[k].iter;
         info[k].rejects = fin[k].rejects;
@@ -1911,11 +2073,14 @@ pdt_status pdt_solve_batch(pdt_problem_t pb, double* const* Pi, const pdt_solve_
         info[k].L_used = Ls[k];
         info[k].seconds = secs;
         info[k].converged = conv ? 1 : 0;
-        info[k].refine_iters = 0;
+        info[k].refine_iters = refined ? fin[k].iter - fin32[k].iter : 0;
         info[k].fell_back_to_cold = 0;
+        info[k].fw_gap = fw;
+        info[k].status = stk;
       }
     }
     HIPCHK(hipStreamSynchronize(s));
+    if (!all_finite) return set_err(PDT_ERR_NUMERIC, "objective is not finite for some instance");
     if (!all_conv) return set_err(PDT_ERR_NOT_CONVERGED, "max_iters reached before the tolerance for some instance");
     g_last_error.clear();
     return PDT_OK;

@@ -64,6 +64,21 @@ __device__ __forceinline__ void decide_body(const double* partials, int n, Solve
   if ((mode == DEC_ITER || mode == DEC_RESYNC) && st->done) return;
   const double s = threadIdx.x < 256 ? strided_sum256(partials, n, threadIdx.x) : 0.0;
   const double f = first256_sum<BS>(s, sh);
+  if (mode == DEC_KKT) {
+    // KKT residual sqrt(mean((X (g - min_n g))^2)) and Frank-Wolfe gap
+    // sum_i (<g_i, X_i> - min_n g_i) of the current iterate
+    __syncthreads();
+    const double s2 = threadIdx.x < 256 ? strided_sum256(partials + n, n, threadIdx.x) : 0.0;
+    const double fw = first256_sum<BS>(s2, sh);
+    if (threadIdx.x != 0) return;
+    st->kkt = sqrt(f / st->mn);
+    st->fw = fw;
+    if (st->kkt_tol > 0.0 && st->kkt <= st->kkt_tol) {
+      st->done = 1;
+      st->kkt_hit = 1;
+    }
+    return;
+  }
   if (threadIdx.x != 0) return;
   if (mode == DEC_EVAL) {
     st->f_eval = f;
@@ -74,6 +89,7 @@ __device__ __forceinline__ void decide_body(const double* partials, int n, Solve
     // FP32 updates, so later acceptance tests compare against the true value
     st->f_cur = f;
     st->f_new = f;
+    if (st->f_star > 0.0 && f - st->f_star <= st->rel_tol * st->f_star) st->done = 1;
     return;
   }
   if (mode == DEC_INIT) {
@@ -85,9 +101,9 @@ __device__ __forceinline__ void decide_body(const double* partials, int n, Solve
     st->ix_prev = 0;
     st->ix_new = 1;
     st->sel_acc = 0;
-    st->iter = 0;
-    st->rejects = 0;
-    st->done = (st->max_iters <= 0) ||
+    // iter and rejects carry on (zero from the host's set-up, or the counts of a
+    // reduced-precision phase that a refinement continues)
+    st->done = (st->iter >= st->max_iters) ||
                (st->f_star > 0.0 && f - st->f_star <= st->rel_tol * st->f_star) ? 1 : 0;
     return;
   }
@@ -112,7 +128,8 @@ __device__ __forceinline__ void decide_body(const double* partials, int n, Solve
   st->t = tt;
   st->beta = (tt - 1.0) / (0.5 * (1.0 + sqrt(1.0 + 4.0 * tt * tt)));
   const long long k = st->iter;
-  if (history) history[k] = st->f_cur;
+  const long long hs = st->hist_stride > 1 ? st->hist_stride : 1;
+  if (history && k % hs == 0) history[k / hs] = st->f_cur;
   st->iter = k + 1;
   if (k + 1 >= st->max_iters) st->done = 1;
   if (st->f_star > 0.0 && st->f_cur - st->f_star <= st->rel_tol * st->f_star) st->done = 1;

@@ -33,7 +33,9 @@ constexpr int kWave = 64;
 // of the mixed path (O, both residual candidates and f of X_cur made exact again)
 enum FxMode { FX_ITER = 0, FX_INIT = 1, FX_EVAL = 2, FX_DELTA = 3, FX_EVAL_PREV = 4, FX_RESYNC = 5 };
 enum FtrMode { FTR_STEP = 0, FTR_GRAD = 1 };
-enum DecideMode { DEC_ITER = 0, DEC_INIT = 1, DEC_EVAL = 2, DEC_RESYNC = 3 };
+// DEC_KKT: the KKT residual and Frank-Wolfe gap of X_cur from a gradient launch's
+// partials ([n] KKT sums, then [n] gap sums), and the KKT stopping test
+enum DecideMode { DEC_ITER = 0, DEC_INIT = 1, DEC_EVAL = 2, DEC_RESYNC = 3, DEC_KKT = 4 };
 
 // Device-resident solver state of one instance.  Written only by the decide kernel
 // (one thread, vector stores), read by every other kernel.
@@ -45,14 +47,18 @@ struct SolverState {
   double beta;     // extrapolation weight for the next transposed-product launch
   double f_star;   // target optimum (<= 0: none)
   double rel_tol;  // stop once f_cur - f_star <= rel_tol * f_star
-  double kkt;      // last KKT residual
+  double kkt;      // last KKT residual (DEC_KKT)
+  double fw;       // last Frank-Wolfe gap (DEC_KKT)
+  double kkt_tol;  // stop once kkt <= kkt_tol (<= 0: no KKT test)
+  double mn;       // M N, the count of the KKT residual's mean
   long long iter;
   long long rejects;
   long long max_iters;
+  long long hist_stride;  // history[k / stride] = f after iteration k, k % stride == 0 (0 acts as 1)
   int ix_cur, ix_prev, ix_new;
   int sel_acc;     // 1: next step uses R_acc, 0: R_rej
   int done;
-  int pad_;
+  int kkt_hit;     // 1: done was set by the KKT test
 };
 
 struct ProbView {
@@ -130,14 +136,25 @@ hipError_t launch_setup_hdiag(const ProbView& pv, double* hdiag, hipStream_t s);
 hipError_t launch_power_normalize(double* G, double* V, int M, int ld, const double* w, double* scratch,
                                   double* lam_out, hipStream_t s);
 hipError_t launch_reduce_sum(const double* partials, int n, double* out, hipStream_t s);
+// batches: out[k] = *st[k]; st[k]->done = 1 where flags[k] != 0
+hipError_t launch_gather_states(SolverState* const* st, int n, SolverState* out, hipStream_t s);
+hipError_t launch_mark_done(SolverState* const* st, const int* flags, int n, hipStream_t s);
 template <typename Ts, typename Td>
 hipError_t launch_convert_pad(const Ts* src, Td* dst, long long rows, int cols, int ld_src, int ld_dst,
                               hipStream_t s);
+
+// Message returned by pdt_last_error() for the calling thread (pdt_capi.hip); "" clears it.
+void set_last_error(const char* msg);
 
 // Long-range smoothing (pdt_smooth.hip); scratch: device [smooth_scratch_doubles(M, N)]
 long long smooth_scratch_doubles(long long M, int N);
 hipError_t launch_smooth_rows(const double* Pi, double* out, long long M, int N, int divisor, long long skip,
                               double* scratch, hipStream_t s);
+
+// R_rej = O[ix_cur] - P over [D][Npad]: the residual of the current iterate, which a
+// gradient launch (FTR_GRAD) reads
+template <typename T>
+hipError_t launch_resid_cur(const Bufs<T>& b, const SolverState* st, long long n, hipStream_t s);
 
 template <typename T>
 hipError_t launch_fill_rows(T* X, long long rows, int cols, int ld, T value, hipStream_t s);

@@ -30,6 +30,18 @@ __global__ __launch_bounds__(256) void decide_batch_kernel(const BatchInst<TS>* 
   decide_body<256>(I.b.partials, I.n_dt, I.st, I.b.history, mode);
 }
 
+// Batches: every instance's state into one array (one copy to the host per chunk), and
+// the host's stop flags into the states (instances whose phase is over).
+__global__ __launch_bounds__(256) void gather_states_kernel(SolverState* const* st, int n, SolverState* out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = *st[k];
+}
+
+__global__ __launch_bounds__(256) void mark_done_kernel(SolverState* const* st, const int* flags, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n && flags[k]) st[k]->done = 1;
+}
+
 __global__ __launch_bounds__(256) void reduce_sum_kernel(const double* partials, int n, double* out) {
   __shared__ double sh[256];
   double s = 0.0;
@@ -205,6 +217,13 @@ __global__ void fill_rows_kernel(T* X, long long rows, int cols, int ld, T value
   X[idx] = c < cols ? value : (T)0;
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void resid_cur_kernel(Bufs<T> b, const SolverState* st, long long n) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  b.R_rej[idx] = b.O[st->ix_cur][idx] - b.P[idx];
+}
+
 template <typename Ts, typename Td>
 __global__ void convert_pad_kernel(const Ts* src, Td* dst, long long rows, int cols, int ld_src,
                                    int ld_dst) {
@@ -239,6 +258,18 @@ template hipError_t launch_decide_batch<float>(const BatchInst<float>*, int, int
 hipError_t launch_decide(const double* partials, int n, SolverState* st, double* history, int mode,
                          hipStream_t s) {
   hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(256), 0, s, partials, n, st, history, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_states(SolverState* const* st, int n, SolverState* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_states_kernel, dim3((n + 255) / 256), dim3(256), 0, s, st, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark_done(SolverState* const* st, const int* flags, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mark_done_kernel, dim3((n + 255) / 256), dim3(256), 0, s, st, flags, n);
   return hipGetLastError();
 }
 
@@ -313,6 +344,15 @@ hipError_t launch_fill_rows(T* X, long long rows, int cols, int ld, T value, hip
                      cols, ld, value);
   return hipGetLastError();
 }
+template <typename T>
+hipError_t launch_resid_cur(const Bufs<T>& b, const SolverState* st, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((resid_cur_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b, st, n);
+  return hipGetLastError();
+}
+template hipError_t launch_resid_cur<double>(const Bufs<double>&, const SolverState*, long long, hipStream_t);
+template hipError_t launch_resid_cur<float>(const Bufs<float>&, const SolverState*, long long, hipStream_t);
+
 template hipError_t launch_fill_rows<double>(double*, long long, int, int, double, hipStream_t);
 template hipError_t launch_fill_rows<float>(float*, long long, int, int, float, hipStream_t);
 

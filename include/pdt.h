@@ -211,6 +211,24 @@ pdt_status pdt_project_simplex(const double* X, double* Y, int64_t rows, int64_t
 pdt_status pdt_smooth_rows(const double* Pi, double* out, int64_t M, int64_t N, int32_t divisor, int64_t skip,
                            void* stream);
 
+/*
+ * pdt_smooth_rows without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and results as pdt_smooth_rows, but the window
+ * sums use a fixed device array of PDT_SMOOTH_NOALLOC_MAX_DOUBLES doubles (64 MiB)
+ * that the library holds on each GPU it runs on until the process ends, instead of
+ * temporary memory.  Sizes with 2 (M + 1 + ceil(M / 256)) N above that limit are
+ * rejected with PDT_ERR_INVALID_ARG (e.g. M = 16384 rows of N <= 255 outcomes fit).
+ * The array's address on the current device is looked up on the first call on that
+ * device; the call then uses the current device, so `stream` must belong to it.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (other
+ * threads, other streams) race and give wrong results; serialise them.  No entry of
+ * the array needs to start at zero (each pass writes what the next reads).
+ */
+#define PDT_SMOOTH_NOALLOC_MAX_DOUBLES (8ll << 20)
+pdt_status pdt_smooth_rows_noalloc(const double* Pi, double* out, int64_t M, int64_t N, int32_t divisor,
+                                   int64_t skip, void* stream);
+
 /* Same, FP32. */
 pdt_status pdt_project_simplex_f32(const float* X, float* Y, int64_t rows, int64_t cols, void* stream);
 

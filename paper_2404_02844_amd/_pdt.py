@@ -133,7 +133,9 @@ def lib() -> ctypes.CDLL:
         L.pdt_newton_direction.argtypes = [vp, ctypes.c_int, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                            vp, vp, ctypes.POINTER(ctypes.c_int64), dp]
         L.pdt_smooth_rows.argtypes = [vp, vp, i64, i64, ctypes.c_int32, i64, vp]
-        for name in ("pdt_newton_solve", "pdt_hessian_apply", "pdt_newton_direction", "pdt_smooth_rows"):
+        L.pdt_smooth_rows_noalloc.argtypes = [vp, vp, i64, i64, ctypes.c_int32, i64, vp]
+        for name in ("pdt_newton_solve", "pdt_hessian_apply", "pdt_newton_direction", "pdt_smooth_rows",
+                     "pdt_smooth_rows_noalloc"):
             getattr(L, name).restype = ctypes.c_int
         L.pdt_last_error.argtypes = []
         L.pdt_last_error.restype = ctypes.c_char_p
@@ -279,6 +281,19 @@ def pdt_smooth_rows(Pi, out=None, divisor: int = 50, skip: int = 100, stream=Non
         out = Pi.new_empty(Pi.shape)
     _check(lib().pdt_smooth_rows(ctypes.c_void_p(Pi.data_ptr()), ctypes.c_void_p(out.data_ptr()), int(Pi.shape[0]),
                                  int(Pi.shape[1]), int(divisor), int(skip), _stream_ptr(stream)))
+    return out
+
+
+# doubles of the fixed device array behind pdt_smooth_rows_noalloc (include/pdt.h)
+SMOOTH_NOALLOC_MAX_DOUBLES = 8 << 20
+
+
+def pdt_smooth_rows_noalloc(Pi, out, divisor: int = 50, skip: int = 100, stream=None):
+    """pdt_smooth_rows on the library's fixed device array: allocates nothing, so `out`
+    (a contiguous float64 [M, N] GPU tensor, may be Pi) must be given."""
+    _check(lib().pdt_smooth_rows_noalloc(ctypes.c_void_p(Pi.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                         int(Pi.shape[0]), int(Pi.shape[1]), int(divisor), int(skip),
+                                         _stream_ptr(stream)))
     return out
 
 

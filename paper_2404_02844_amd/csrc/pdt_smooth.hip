@@ -15,6 +15,11 @@
 // entry, so the output may overwrite the input.
 #include <hip/hip_runtime.h>
 
+#include <climits>
+#include <mutex>
+#include <string>
+
+#include "pdt.h"
 #include "pdt_internal.h"
 
 namespace pdt {
@@ -155,3 +160,79 @@ hipError_t launch_smooth_rows(const double* Pi, double* out, long long M, int N,
 }
 
 }  // namespace pdt
+
+// ---------------------------------------------------------------------------------------
+// Allocation-free smoothing: the same kernels on a fixed device array instead of memory
+// allocated per call.  Each GPU the library runs on holds its own copy of the array
+// until the process ends; in host code the array's name is not a device address, so
+// its address is looked up once per device and only that address is handed to kernels.
+// ---------------------------------------------------------------------------------------
+constexpr long long kNoAllocScratchDoubles = PDT_SMOOTH_NOALLOC_MAX_DOUBLES;  // 64 MiB
+
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's copy of `scratch` (the current device), looked up on
+// the first call on that device.
+hipError_t scratch_address(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+pdt_status pdt_smooth_rows_noalloc(const double* Pi, double* out, int64_t M, int64_t N, int32_t divisor,
+                                   int64_t skip, void* stream) {
+  if (!Pi || !out) {
+    pdt::set_last_error("Pi and out must not be NULL");
+    return PDT_ERR_INVALID_ARG;
+  }
+  if (M < 1 || N < 1 || M * N > (int64_t)INT_MAX) {
+    pdt::set_last_error("need M, N >= 1, M*N < 2^31");
+    return PDT_ERR_INVALID_ARG;
+  }
+  if (divisor < 1 || skip < 0) {
+    pdt::set_last_error("need divisor >= 1, skip >= 0");
+    return PDT_ERR_INVALID_ARG;
+  }
+  const long long need = pdt::smooth_scratch_doubles((long long)M, (int)N);
+  if (need > kNoAllocScratchDoubles) {
+    pdt::set_last_error(("scratch of " + std::to_string(need) + " doubles exceeds the fixed " +
+                    std::to_string(kNoAllocScratchDoubles) + " (2 (M + 1 + ceil(M / 256)) N must be <= that)")
+                       .c_str());
+    return PDT_ERR_INVALID_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* buf = nullptr;
+  hipError_t e = scratch_address(&buf);
+  if (e == hipSuccess) e = pdt::launch_smooth_rows(Pi, out, (long long)M, (int)N, (int)divisor, (long long)skip, buf, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    pdt::set_last_error(hipGetErrorString(e));
+    return PDT_ERR_DEVICE;
+  }
+  pdt::set_last_error("");
+  return PDT_OK;
+}
+
+}  // extern "C"

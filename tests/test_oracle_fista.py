@@ -226,3 +226,49 @@ def test_constant_weights_give_the_plain_iteration(c1):
     a = fista.fista_r(F, inst.P, inst.gamma, L, 200)
     b = fista.fista_r(F, inst.P, inst.gamma, L, 200, row_w=np.ones(inst.M))
     assert np.array_equal(a.X, b.X)
+
+
+def test_momentum_schedule_hand_computed():
+    """Three iterations on a problem small enough to follow by hand: F = I (two probes, two
+    photon numbers), gamma = 0, P = [[0.9, 0.1], [0.2, 0.8]], L_hat = 20, from Pi = 1/N.
+    The expected values were computed with 40-digit arithmetic straight from the
+    definitions -- t_1 = 1, t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2, beta_k = (t_k - 1) /
+    t_{k+1}, Y = X_k + beta_k (X_k - X_{k-1}), gradient 2 (Y - P), and the two-outcome
+    projection a = clip((y_1 - y_2 + 1) / 2, 0, 1) -- with no code shared with the
+    oracle.  Every step is accepted, with beta = 0, 0.28175..., 0.43404...; the schedules
+    beta_k = (t_{k+1} - 1) / t_{k+1} and k / (k + 3) move the third iterate by 2.2e-2 and
+    2.9e-3."""
+    F = np.eye(2)
+    P = np.array([[0.9, 0.1], [0.2, 0.8]])
+    expected = [
+        ([0.54, 0.46, 0.47, 0.53], 0.405),
+        ([0.58614312690451154945, 0.41385687309548845055, 0.43539265482161633791, 0.56460734517838366209],
+         0.30783167746649231875),
+        ([0.63555409630109732847, 0.36444590369890267153, 0.39833442777417700365, 0.60166557222582299635],
+         0.21853636244727908016),
+    ]
+    for k, (X, f) in enumerate(expected, start=1):
+        r = fista.fista_r(F, P, 0.0, 20.0, k)
+        assert r.rejects == 0 and r.iters == k
+        assert np.max(np.abs(r.X.ravel() - np.array(X))) < 1e-14
+        assert r.f == pytest.approx(f, rel=1e-14)
+
+
+def test_fw_gap_closed_forms():
+    """With F = I and gamma = 0 the gradient is 2 (Pi - P), which gives the Frank-Wolfe gap
+    in closed form: at Pi = 1/N each row contributes 2 (max_n P_in - 1/N) (its inner
+    product with the gradient vanishes); at a vertex e_j it contributes 2 (1 - P_ij +
+    max_{n != j} P_in); at Pi = P it is zero."""
+    rng = np.random.default_rng(11)
+    M, N = 7, 5
+    P = simplex.project_rows(rng.random((M, N)))
+    F = np.eye(M)
+    U = np.full((M, N), 1.0 / N)
+    assert certify.fw_gap(F, P, U, 0.0) == pytest.approx(2.0 * np.sum(P.max(1) - 1.0 / N), rel=1e-14)
+    j = rng.integers(0, N, size=M)
+    V = np.zeros((M, N))
+    V[np.arange(M), j] = 1.0
+    others = np.where(np.arange(N)[None, :] == j[:, None], -np.inf, P).max(1)
+    want = 2.0 * np.sum(1.0 - P[np.arange(M), j] + others)
+    assert certify.fw_gap(F, P, V, 0.0) == pytest.approx(want, rel=1e-14)
+    assert abs(certify.fw_gap(F, P, P, 0.0)) < 1e-15

@@ -346,16 +346,28 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
       }
       if (iter) {
         const T oc = oc_;
-        b.R_acc[off] = o + beta_acc * (o - oc) - pv_;
-        b.R_rej[off] = oc - pv_;
+        const T ra = o + beta_acc * (o - oc) - pv_, rr = oc - pv_;
+        b.R_acc[off] = ra;
+        b.R_rej[off] = rr;
+        if (b.R32_acc) {
+          b.R32_acc[off] = (float)ra;
+          b.R32_rej[off] = (float)rr;
+        }
       } else if (mode == FX_RESYNC) {
         // the next step's residual if it keeps its momentum (F Y = O + beta (O - O_prev))
         // or restarts, both from exact products
         const T op = b.O[st->ix_prev][off];
-        b.R_acc[off] = o + (T)st->beta * (o - op) - pv_;
-        b.R_rej[off] = o - pv_;
+        const T ra = o + (T)st->beta * (o - op) - pv_, rr = o - pv_;
+        b.R_acc[off] = ra;
+        b.R_rej[off] = rr;
+        if (b.R32_acc) {
+          b.R32_acc[off] = (float)ra;
+          b.R32_rej[off] = (float)rr;
+        }
       } else if (mode != FX_EVAL_PREV) {
-        b.R_rej[off] = o - pv_;
+        const T rr = o - pv_;
+        b.R_rej[off] = rr;
+        if (b.R32_rej) b.R32_rej[off] = (float)rr;
       }
     }
   }
@@ -415,6 +427,10 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
   const int dlo = pv.mt_dlo[mt];
   const int dhi = pv.mt_dhi[mt];
   const T* __restrict__ R = (mode == FTR_STEP && st->sel_acc) ? b.R_acc : b.R_rej;
+  // FP32 operands on FP64 storage (the mixed path) read the FP32 copies of R the forward
+  // product wrote (the same values as converting R at the load, at half the bytes)
+  constexpr bool kR32 = !std::is_same<TS, TC>::value;
+  const float* __restrict__ R32 = (mode == FTR_STEP && st->sel_acc) ? b.R32_acc : b.R32_rej;
 
   // probes beyond dhi are clamped: their generated F entries are zero
   auto load_r = [&](int drow, TC (&dst)[NTC], int nt0) {
@@ -422,7 +438,10 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
     const unsigned base = (unsigned)(dd > 0 ? dd : 0) * (unsigned)Npad + (unsigned)i;
 #pragma unroll
     for (int k = 0; k < NTC; ++k)
-      if (NPASS == 1 || nt0 + k < NT) dst[k] = (TC)R[base + 16u * (nt0 + k)];
+      if (NPASS == 1 || nt0 + k < NT) {
+        if constexpr (kR32) dst[k] = (TC)R32[base + 16u * (nt0 + k)];
+        else dst[k] = (TC)R[base + 16u * (nt0 + k)];
+      }
   };
   const int nchunks = dhi >= dlo ? (dhi - dlo) / kChunkD + 1 : 0;
   // wave wv takes chunks wv, wv + KS, ...: its rounds end with its last nonempty chunk
@@ -647,16 +666,20 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
 
 
 // two waves per SIMD: the forward product's loads and recursion are latency-bound
+// Workgroups are dispatched in blockIdx order, and the band work of a tile grows with its
+// photon numbers (probe means): the grid runs from the last tile to the first, so the
+// heaviest tiles start first and the light ones fill the tail of the launch.  Each tile
+// still writes its own partials, so the order of every sum is unchanged.
 template <typename TS, typename TC, int NT, int KS>
 __global__ __launch_bounds__(64 * KS) __attribute__((amdgpu_waves_per_eu(2))) void fx_kernel(ProbView pv, Bufs<TS> b,
                                                                                             SolverState* st, int mode) {
-  fx_body<TS, TC, NT, KS>(pv, b, st, mode, blockIdx.x, gridDim.x);
+  fx_body<TS, TC, NT, KS>(pv, b, st, mode, gridDim.x - 1 - blockIdx.x, gridDim.x);
 }
 
 template <typename TS, typename TC, int NT, int KS>
 __global__ __launch_bounds__(64 * KS) void ftr_kernel(ProbView pv, Bufs<TS> b, SolverState* st, int mode,
                                                        double step) {
-  ftr_body<TS, TC, NT, KS>(pv, b, st, mode, step, blockIdx.x);
+  ftr_body<TS, TC, NT, KS>(pv, b, st, mode, step, gridDim.x - 1 - blockIdx.x);
 }
 
 // Batched launches: one workgroup per (instance, tile) item of a work list; every

@@ -69,6 +69,8 @@ enum Variant { VAR_FP64 = 0, VAR_FP32 = 1, VAR_MIXED = 2 };
 template <typename T>
 struct Work {
   float* dX = nullptr;  // FP32 X_new - X_cur of the mixed path (FP64 storage only)
+  float* R32_acc = nullptr;  // FP32 copies of R_acc / R_rej for the mixed path's transposed product
+  float* R32_rej = nullptr;
   T* X[3] = {nullptr, nullptr, nullptr};
   T* O[3] = {nullptr, nullptr, nullptr};
   T* R_acc = nullptr;
@@ -256,8 +258,10 @@ ProbView view_var(const Instance& I, int var) {
   return pv;
 }
 
+// r32: also hand the kernels the FP32 residual copies (the mixed path's launches)
 template <typename T>
-Bufs<T> bufs_of(const Instance& I, const Work<T>& w, double* history, const double* wrow = nullptr) {
+Bufs<T> bufs_of(const Instance& I, const Work<T>& w, double* history, const double* wrow = nullptr,
+                bool r32 = false) {
   Bufs<T> b;
   for (int k = 0; k < 3; ++k) {
     b.X[k] = w.X[k];
@@ -274,6 +278,10 @@ Bufs<T> bufs_of(const Instance& I, const Work<T>& w, double* history, const doub
   b.history = history;
   b.wrow = wrow;
   b.dX = w.dX;
+  if (r32) {
+    b.R32_acc = w.R32_acc;
+    b.R32_rej = w.R32_rej;
+  }
   return b;
 }
 
@@ -726,11 +734,13 @@ void run_mixed(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double s
   hipStream_t s = pb->stream;
   const bool kkt = o.kkt_tol > 0;
   if (!I.w64.dX) {
-    const size_t xm = (size_t)I.M * I.Npad;
+    const size_t xm = (size_t)I.M * I.Npad, od = (size_t)I.D * I.Npad;
     I.w64.dX = pb->arena.alloc<float>(xm);
+    I.w64.R32_acc = pb->arena.alloc<float>(od);
+    I.w64.R32_rej = pb->arena.alloc<float>(od);
     HIPCHK(hipMemsetAsync(I.w64.dX, 0, xm * sizeof(float), s));
   }
-  Bufs<double> b = bufs_of(I, I.w64, o.history, wrow);
+  Bufs<double> b = bufs_of(I, I.w64, o.history, wrow, true);
   start_from_x0<double>(pb, I, b, VAR_FP64, kkt);
   SolverState h = run_chunks<double, float>(pb, I, VAR_MIXED, b, step, kStallMixed, kkt);
   const int64_t mixed_iters = h.iter;
@@ -741,7 +751,9 @@ void run_mixed(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double s
     enqueue_resync<double>(view_var(I, VAR_FP64), b, I.st, s);
     h = read_state(s, I.st);
   }
-  if (!h.done && !o.skip_refine) h = run_chunks<double, double>(pb, I, VAR_FP64, b, step, 0.0, kkt);
+  // the refinement's FP64 launches need no FP32 residual copies
+  if (!h.done && !o.skip_refine)
+    h = run_chunks<double, double>(pb, I, VAR_FP64, bufs_of(I, I.w64, o.history, wrow), step, 0.0, kkt);
   refine_iters = h.iter - mixed_iters;
   out = h;
 }
@@ -768,6 +780,9 @@ void run_fp32(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double st
                                            s));
   const int64_t fp32_iters = h.iter;
   if (!o.skip_refine && h.iter < h.max_iters) {
+    // FP32 rows sum to 1 only to FP32 rounding; the FP64 method starts on the constraint
+    // set (an infeasible start can undercut every feasible step's objective and stall)
+    HIPCHK(launch_project_rows<double>(I.w64.X[0], I.w64.X[0], (long long)M, (int)I.N, (int)Np, (int)Np, s));
     // every FP32-phase stop is provisional: the FP64 start re-tests it on exact values
     write_state(s, I.st, restart_state(h));
     Bufs<double> b64 = bufs_of(I, I.w64, o.history, wrow);
@@ -1076,7 +1091,7 @@ void replay_impl(pdt_problem_s* pb, Instance& I, int kernel, int64_t reps) {
   hipStream_t s = pb->stream;
   const int var = std::is_same<T, float>::value ? VAR_FP32 : (std::is_same<T, TC>::value ? VAR_FP64 : VAR_MIXED);
   const ProbView pv = view_var(I, var);
-  Bufs<T> b = bufs_of(I, work_of<T>(I), nullptr);
+  Bufs<T> b = bufs_of(I, work_of<T>(I), nullptr, nullptr, var == VAR_MIXED);
   SolverState s0;
   std::memset(&s0, 0, sizeof(s0));
   s0.ix_cur = 0;
@@ -2034,6 +2049,14 @@ pdt_status pdt_solve_batch(pdt_problem_t pb, double* const* Pi, const pdt_solve_
       }
       fin = fin32;
       if (!o.skip_refine) {
+        // as in a single solve: the instances with iterations left start the FP64 phase
+        // from their projected iterate, the others keep the FP32 result as it is
+        for (size_t k = 0; k < n; ++k) {
+          Instance& I = pb->inst[k];
+          if (fin32[k].iter < fin32[k].max_iters)
+            HIPCHK(launch_project_rows<double>(I.w64.X[0], I.w64.X[0], (long long)I.M, (int)I.N, (int)I.Npad,
+                                               (int)I.Npad, s));
+        }
         // FP64 refinement of every instance together: each starts from its promoted
         // iterate with fresh momentum and its remaining iterations; an instance whose
         // exact objective already meets its tolerance (or that has none left) stops at once

@@ -15,6 +15,7 @@
 //   R_acc, R_rej [D][Npad] residual F Y - P for the next step, if the candidate is
 //                         accepted / rejected (both formed before the decision)
 //   dX      [M][Npad]     FP32 candidate step X_new - X_cur (mixed path only)
+//   R32_acc, R32_rej [D][Npad] FP32 copies of the residual candidates (mixed path only)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -99,6 +100,9 @@ struct Bufs {
   unsigned* fx_count = nullptr;  // [tiles] finished workgroups per tile, zero between launches
   const int* skip = nullptr;     // when set and *skip != 0 the launch returns at once (the
                                  // Hessian products of a conjugate-gradient solve that stopped)
+  float* R32_acc = nullptr;      // [D][Npad] FP32 copies of R_acc / R_rej (mixed path): every
+  float* R32_rej = nullptr;      // forward-product epilogue that writes R writes them too, and
+                                 // the FP32-operand transposed product reads them instead of R
 };
 
 // One instance of a batched launch: its problem view, buffers, state and step; n_dt

@@ -17,6 +17,16 @@ linear), exactly as it is written in the definition of the iteration; F X' is a
 fresh product.  After a reset beta = 0, so the next step is a plain projected
 gradient step of length 1/L_hat, which decreases f when L_hat >= lambda_max.
 
+Gradient restart (optional, restart="gradient"): the adaptive restart of O'Donoghue and
+Candes (2015), in its gradient form.  After an accepted step the momentum is also reset
+(t = 1, so the next beta is 0) when the step X' - X_k points against the gradient-mapping
+direction Y - X', measured in the metric of the step (the variables W^{-1/2} Pi of the
+row-scaled step):
+
+    sum_m (1 / w_m) sum_n (Y - X')[m, n] (X' - X_k)[m, n] > 0.
+
+The reject-and-reset of a step that raises f stays as it is.
+
 L_hat = 1.05 * lambda_max(2 F^T F + 2 gamma L), lambda_max from 100 power iterations
 started at the unit vector 1/sqrt(M): lambda_k = ||H v_{k-1}||, v_k = H v_{k-1} / lambda_k.
 
@@ -107,12 +117,17 @@ class FistaResult:
 def fista_r(F, P: np.ndarray, gamma: float, L_hat: float, iters: int,
             X0: np.ndarray | None = None, exact_sums: bool = True,
             f_star: float | None = None, rel_tol: float | None = None,
-            row_w: np.ndarray | None = None) -> FistaResult:
-    """row_w: per-row step weights w (the step of row m is w_m / L_hat); None: w = 1."""
+            row_w: np.ndarray | None = None, restart: str = "function") -> FistaResult:
+    """row_w: per-row step weights w (the step of row m is w_m / L_hat); None: w = 1.
+    restart: "function" (reject a step that raises f and reset) or "gradient" (also reset
+    the momentum after an accepted step that fails the gradient test)."""
+    if restart not in ("function", "gradient"):
+        raise ValueError(restart)
     M = F.shape[1]
     N = P.shape[1]
     X = project_rows(np.full((M, N), 1.0 / N) if X0 is None else X0)
     s = 1.0 / L_hat if row_w is None else (np.asarray(row_w, dtype=np.float64) / L_hat)[:, None]
+    inv_w = np.ones((M, 1)) if row_w is None else 1.0 / np.asarray(row_w, dtype=np.float64)[:, None]
 
     def fval(O, Xc):
         return sum_squares(O - P, exact_sums) + regulariser(Xc, gamma, exact_sums)
@@ -138,9 +153,10 @@ def fista_r(F, P: np.ndarray, gamma: float, L_hat: float, iters: int,
             t = 1.0
             rejects += 1
         else:
+            reset = restart == "gradient" and float(np.sum(inv_w * (Y - Xn) * (Xn - X))) > 0.0
             Xp, Op = X, O
             X, O, f = Xn, On, fn
-            t = tn
+            t = 1.0 if reset else tn
         hist[k] = f
         k_done = k + 1
         if f_star is not None and rel_tol is not None and (f - f_star) <= rel_tol * f_star:

@@ -272,3 +272,45 @@ def test_fw_gap_closed_forms():
     want = 2.0 * np.sum(1.0 - P[np.arange(M), j] + others)
     assert certify.fw_gap(F, P, V, 0.0) == pytest.approx(want, rel=1e-14)
     assert abs(certify.fw_gap(F, P, P, 0.0)) < 1e-15
+
+
+def test_gradient_restart_hand_computed():
+    """The gradient restart on the 2x2 problem above (F = I, gamma = 0, Pi = 1/N start),
+    computed with 40-digit arithmetic from the definitions, with the step test
+    sum_m (1 / w_m) sum_n (Y - X')(X' - X_k) > 0 after each accepted step.
+    (a) P = [[0.9, 0.1], [0.2, 0.8]], L_hat = 3: the third step triggers the reset, so the
+        fourth is a plain projected step (beta 0 instead of 0.531...); the function
+        restart alone keeps the momentum and lands elsewhere.
+    (b) P = [[0.9, 0.1], [0.6, 0.4]], L_hat = 3.5, row weights (1, 0.5): the reset comes
+        after the fourth step in the weighted metric (after the third without the 1/w_m
+        weights)."""
+    F = np.eye(2)
+    Pa = np.array([[0.9, 0.1], [0.2, 0.8]])
+    want_a = [0.903339154488979523997, 0.0966608455110204760029, 0.197495634133265357002, 0.802504365866734642998]
+    r = fista.fista_r(F, Pa, 0.0, 3.0, 4, restart="gradient")
+    assert r.rejects == 0
+    assert np.max(np.abs(r.X.ravel() - np.array(want_a))) < 1e-14
+    assert r.f == pytest.approx(0.000034843602191475331396, rel=1e-12)
+    plain = fista.fista_r(F, Pa, 0.0, 3.0, 4)
+    want_plain = [0.908546615718376670023, 0.0914533842816233299769, 0.193590038211217497483, 0.806409961788782502517]
+    assert np.max(np.abs(plain.X.ravel() - np.array(want_plain))) < 1e-14
+    Pb = np.array([[0.9, 0.1], [0.6, 0.4]])
+    w = np.array([1.0, 0.5])
+    want_b4 = [0.912866395339553487938, 0.0871336046604465120624, 0.590678377762060860622, 0.409321622237939139378]
+    want_b5 = [0.905514169431237209116, 0.0944858305687627908839, 0.593341698401472043301, 0.406658301598527956699]
+    for k, want in ((4, want_b4), (5, want_b5)):
+        r = fista.fista_r(F, Pb, 0.0, 3.5, k, row_w=w, restart="gradient")
+        assert np.max(np.abs(r.X.ravel() - np.array(want))) < 1e-14, k
+    assert r.f == pytest.approx(0.00014947808938670165948, rel=1e-12)
+
+
+def test_gradient_restart_reaches_the_certified_optimum(c1):
+    inst, F = c1
+    with open(os.path.join(GOLDEN, "c1_oracle.json")) as fh:
+        gold = json.load(fh)
+    w = fista.row_weights(F, inst.gamma, inst.M)
+    Lw = fista.lipschitz_scaled(F, inst.gamma, inst.M, w)
+    r = fista.fista_r(F, inst.P, inst.gamma, Lw, 20000, exact_sums=False, row_w=w, restart="gradient")
+    assert np.all(np.diff(r.history) <= 0)
+    assert abs(r.f - gold["f_star"]) <= 1e-12 * gold["f_star"]
+    assert np.max(np.abs(r.X - np.array(gold["Pi_star"]))) <= 2e-6

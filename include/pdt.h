@@ -82,6 +82,19 @@ typedef enum {
   PDT_STEP_DIAG = 1
 } pdt_step_scaling;
 
+/*
+ * Momentum restart.  FUNCTION: a step that raises f is rejected and the momentum reset
+ * (t = 1), the monotone restart of the method as defined above.  GRADIENT: in addition,
+ * an accepted step resets the momentum when it points against the gradient mapping,
+ * sum_m (1 / w_m) sum_n (Y - X_new)[m][n] (X_new - X_cur)[m][n] > 0 (the adaptive
+ * restart of O'Donoghue and Candes, 2015, in the metric of the step; w_m = 1 for the
+ * uniform step).
+ */
+typedef enum {
+  PDT_RESTART_FUNCTION = 0,
+  PDT_RESTART_GRADIENT = 1
+} pdt_restart;
+
 typedef struct pdt_model_s* pdt_model_t;
 
 /* One tomography instance (arguments follow Eq. min and Eq. Fmatrix). */
@@ -133,6 +146,7 @@ typedef struct {
                              reduced-precision phase stalls or meets a tolerance on its own
                              inexact values; 1 stop at the reduced-precision result */
   int64_t history_stride; /* spacing of the history entries (0 or 1: every iteration) */
+  int restart;            /* pdt_restart */
 } pdt_solve_opts;
 
 typedef struct {

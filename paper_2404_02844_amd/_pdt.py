@@ -33,6 +33,9 @@ PDT_INIT_LEARNED = 2
 PDT_STEP_UNIFORM = 0
 PDT_STEP_DIAG = 1
 
+PDT_RESTART_FUNCTION = 0
+PDT_RESTART_GRADIENT = 1
+
 STATUS_NAMES = {0: "PDT_OK", 1: "PDT_ERR_INVALID_ARG", 2: "PDT_ERR_OUT_OF_MEMORY", 3: "PDT_ERR_DEVICE",
                 4: "PDT_ERR_NOT_CONVERGED", 5: "PDT_ERR_NUMERIC"}
 
@@ -54,7 +57,8 @@ class pdt_solve_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("init", ctypes.c_int), ("max_iters", ctypes.c_int64),
                 ("rel_obj_tol", ctypes.c_double), ("f_star", ctypes.c_double), ("step_L", ctypes.c_double),
                 ("history", ctypes.c_void_p), ("model", ctypes.c_void_p), ("scaling", ctypes.c_int),
-                ("kkt_tol", ctypes.c_double), ("skip_refine", ctypes.c_int), ("history_stride", ctypes.c_int64)]
+                ("kkt_tol", ctypes.c_double), ("skip_refine", ctypes.c_int), ("history_stride", ctypes.c_int64),
+                ("restart", ctypes.c_int)]
 
 
 class pdt_solve_info(ctypes.Structure):
@@ -206,7 +210,7 @@ def pdt_destroy_problem(handle) -> None:
 
 def pdt_solve(handle, Pi, *, precision=PDT_FP64, init=PDT_INIT_UNIFORM, max_iters=1000, rel_obj_tol=0.0,
               f_star=0.0, step_L=0.0, history=None, model=None, scaling=PDT_STEP_UNIFORM, kkt_tol=0.0,
-              skip_refine=False, history_stride=1, allow_not_converged=True) -> dict:
+              skip_refine=False, history_stride=1, restart=PDT_RESTART_FUNCTION, allow_not_converged=True) -> dict:
     """Solve in place: ``Pi`` is a contiguous float64 [M, N] GPU tensor."""
     if model is not None and init == PDT_INIT_UNIFORM:
         init = PDT_INIT_LEARNED
@@ -215,7 +219,7 @@ def pdt_solve(handle, Pi, *, precision=PDT_FP64, init=PDT_INIT_UNIFORM, max_iter
                        history=ctypes.c_void_p(history.data_ptr()) if history is not None else None,
                        model=(model.handle if isinstance(model, Model) else model), scaling=int(scaling),
                        kkt_tol=float(kkt_tol), skip_refine=int(bool(skip_refine)),
-                       history_stride=int(history_stride))
+                       history_stride=int(history_stride), restart=int(restart))
     info = pdt_solve_info()
     st = _check(lib().pdt_solve(handle, ctypes.c_void_p(Pi.data_ptr()), ctypes.byref(o), ctypes.byref(info)),
                 allow=(PDT_ERR_NOT_CONVERGED,) if allow_not_converged else ())
@@ -520,14 +524,14 @@ class BatchProblem:
         self.handle = out
 
     def solve(self, Pis, *, precision=PDT_FP64, init=PDT_INIT_UNIFORM, max_iters=1000, rel_obj_tol=0.0,
-              f_star=None, step_L=0.0, scaling=PDT_STEP_UNIFORM, skip_refine=False):
+              f_star=None, step_L=0.0, scaling=PDT_STEP_UNIFORM, skip_refine=False, restart=PDT_RESTART_FUNCTION):
         """Every instance's dict carries its own "status"; the call's own is "batch_status"."""
         import numpy as np
         n = len(self.instances)
         ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() for t in Pis])
         o = pdt_solve_opts(precision=precision, init=init, max_iters=int(max_iters), rel_obj_tol=float(rel_obj_tol),
                            f_star=0.0, step_L=float(step_L), history=None, model=None, scaling=int(scaling),
-                           skip_refine=int(bool(skip_refine)))
+                           skip_refine=int(bool(skip_refine)), restart=int(restart))
         fs = None
         if f_star is not None:
             self._fs = np.ascontiguousarray(f_star, dtype=np.float64)

@@ -29,6 +29,7 @@
 #include <cmath>
 #include <type_traits>
 
+#include "pdt_decide.h"
 #include "pdt_device.h"
 #include "pdt_internal.h"
 #include "pdt_pmf.h"
@@ -205,6 +206,11 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
     for (int q = 0; q < PF; ++q) load_step(mlo + kChunkM * c0 + 4 * q + kq, xb[q], rb[q], 0);
   }
 
+  // With the gradient restart, an accepted candidate whose step fails the test resets the
+  // momentum: the residual handed to the next step is then F X_new - P (beta 0).  The
+  // test is the decision kernel's own sum, in its order.
+  const bool reset = (iter && b.rpart) ? restart_test<64 * KS>(b.rpart, (M + 15) / 16) : false;
+
   // Work of the epilogue that does not depend on the contraction is done here so that its
   // loads overlap the main loop: the regulariser over this workgroup's slice of row
   // pairs, and (when registers allow) O_cur and P of this group's output row.
@@ -318,7 +324,7 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
 
   // epilogue: wave wv finishes probe rows 4 wv + kq
   T beta_acc = 0;
-  if (iter) {
+  if (iter && !reset) {
     const double t = st->t;
     const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
     const double tnn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * tn * tn));
@@ -576,7 +582,7 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
     // the mixed instantiation also hands the forward product the step X_new - X_cur in FP32
     constexpr bool delta = !std::is_same<TS, TC>::value;
     T z[1][NT];
-    T xcs[NT];
+    T xcs[NT], ys[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const int n = nt * 16 + i;
@@ -589,6 +595,7 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
         form_y(nt, xc, y, ly);
       }
       xcs[nt] = xc;
+      ys[nt] = y;
       T zz = (n < N) ? (T)0 : neg_huge<T>();
       if (mval && n < N) {
         const T g = (T)2 * (T)S[(4 * wv + kq) * LDT + n] + g2 * ly;
@@ -598,6 +605,7 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
     }
     T tau[1];
     simplex_threshold<T, 16, NT, 1, 8>(z, tau);
+    double rr = 0.0;  // this row's gradient-restart term, sum_n (Y - X_new)(X_new - X_cur) / w_m
     if (mval) {
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
@@ -605,6 +613,19 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
         const T xn = (n < N) ? fmax(z[0][nt] - tau[0], (T)0) : (T)0;
         Xn[(size_t)m * Npad + n] = xn;
         if constexpr (delta) b.dX[(size_t)m * Npad + n] = (float)(xn - xcs[nt]);
+        if (n < N) rr += ((double)ys[nt] - (double)xn) * ((double)xn - (double)xcs[nt]);
+      }
+      if (b.wrow) rr /= b.wrow[m];
+    }
+    if (b.rpart) {
+      rr = group_sum<64>(rr);
+      if (lane == 0) red[wv] = rr;
+      __syncthreads();
+      if (tid == 0) {
+        double sr = 0.0;
+#pragma unroll
+        for (int w = 0; w < KS; ++w) sr += red[w];
+        b.rpart[mt] = sr;
       }
     }
   } else {

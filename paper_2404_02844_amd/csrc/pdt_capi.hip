@@ -138,6 +138,7 @@ struct Instance {
   Work<float> w32;
   double* partials = nullptr;
   int n_partials = 0;
+  double* rpart = nullptr;  // [ceil(M / 16)] gradient-restart partials of the step
   SolverState* st = nullptr;
   SolverState* st_eval = nullptr;
   double* scalar = nullptr;
@@ -148,6 +149,7 @@ struct Instance {
   double* graph_hist[3] = {nullptr, nullptr, nullptr};
   const double* graph_w[3] = {nullptr, nullptr, nullptr};
   bool graph_kkt[3] = {false, false, false};
+  const double* graph_rp[3] = {nullptr, nullptr, nullptr};
   // waves per workgroup forced per variant and kernel (0: from the tuning table)
   int ks_force[3][2] = {{0, 0}, {0, 0}, {0, 0}};
   // split contraction of the forward product: workgroups per 16-probe tile
@@ -177,6 +179,7 @@ struct LaunchList {
 struct BatchPlan {
   int prec = -1;
   int scaling = -1;
+  int restart = -1;
   std::vector<double> steps;
   void* insts = nullptr;          // device BatchInst<T>[n]
   std::vector<LaunchList> fx, ftr;
@@ -258,10 +261,11 @@ ProbView view_var(const Instance& I, int var) {
   return pv;
 }
 
-// r32: also hand the kernels the FP32 residual copies (the mixed path's launches)
+// r32: also hand the kernels the FP32 residual copies (the mixed path's launches);
+// restart: the gradient restart's partials (pdt_restart)
 template <typename T>
 Bufs<T> bufs_of(const Instance& I, const Work<T>& w, double* history, const double* wrow = nullptr,
-                bool r32 = false) {
+                bool r32 = false, int restart = PDT_RESTART_FUNCTION) {
   Bufs<T> b;
   for (int k = 0; k < 3; ++k) {
     b.X[k] = w.X[k];
@@ -282,6 +286,7 @@ Bufs<T> bufs_of(const Instance& I, const Work<T>& w, double* history, const doub
     b.R32_acc = w.R32_acc;
     b.R32_rej = w.R32_rej;
   }
+  if (restart == PDT_RESTART_GRADIENT) b.rpart = I.rpart;
   return b;
 }
 
@@ -489,6 +494,7 @@ void setup_instance(pdt_problem_s* pb, Instance& I, const pdt_problem_desc& d) {
   // and for the gradient launch's KKT and Frank-Wolfe partials (2 per row tile)
   I.n_partials = (int)std::max(n_dt * (kMaxFxSplit + 1), 2 * n_mt);
   I.partials = A.alloc<double>(I.n_partials);
+  I.rpart = A.alloc<double>(n_mt);
   I.st = A.alloc<SolverState>(1);
   I.st_eval = A.alloc<SolverState>(1);
   I.scalar = A.alloc<double>(4);
@@ -603,7 +609,7 @@ void enqueue_iters(const ProbView& pv, const Bufs<TS>& b, SolverState* st, doubl
   for (int64_t k = 0; k < n; ++k) {
     HIPCHK((launch_ftr<TS, TC>(pv, b, st, FTR_STEP, step, s)));
     HIPCHK((launch_fx<TS, TC>(pv, b, st, delta ? FX_DELTA : FX_ITER, s)));
-    HIPCHK(launch_decide(b.partials, nfx, st, b.history, DEC_ITER, s));
+    HIPCHK(launch_decide(b.partials, nfx, st, b.history, DEC_ITER, s, b.rpart, ftr_num_waves(pv)));
   }
 }
 
@@ -647,7 +653,7 @@ void drop_graphs(Instance& I) {
 template <typename TS, typename TC>
 hipGraphExec_t get_graph(pdt_problem_s* pb, Instance& I, int var, const Bufs<TS>& b, double step, bool kkt) {
   if (I.graph[var] && I.graph_step[var] == step && I.graph_hist[var] == b.history && I.graph_w[var] == b.wrow &&
-      I.graph_kkt[var] == kkt)
+      I.graph_kkt[var] == kkt && I.graph_rp[var] == b.rpart)
     return I.graph[var];
   if (I.graph[var]) (void)hipGraphExecDestroy(I.graph[var]);
   I.graph[var] = nullptr;
@@ -678,6 +684,7 @@ hipGraphExec_t get_graph(pdt_problem_s* pb, Instance& I, int var, const Bufs<TS>
   I.graph_hist[var] = b.history;
   I.graph_w[var] = b.wrow;
   I.graph_kkt[var] = kkt;
+  I.graph_rp[var] = b.rpart;
   return ge;
 }
 
@@ -740,7 +747,7 @@ void run_mixed(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double s
     I.w64.R32_rej = pb->arena.alloc<float>(od);
     HIPCHK(hipMemsetAsync(I.w64.dX, 0, xm * sizeof(float), s));
   }
-  Bufs<double> b = bufs_of(I, I.w64, o.history, wrow, true);
+  Bufs<double> b = bufs_of(I, I.w64, o.history, wrow, true, o.restart);
   start_from_x0<double>(pb, I, b, VAR_FP64, kkt);
   SolverState h = run_chunks<double, float>(pb, I, VAR_MIXED, b, step, kStallMixed, kkt);
   const int64_t mixed_iters = h.iter;
@@ -753,7 +760,8 @@ void run_mixed(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double s
   }
   // the refinement's FP64 launches need no FP32 residual copies
   if (!h.done && !o.skip_refine)
-    h = run_chunks<double, double>(pb, I, VAR_FP64, bufs_of(I, I.w64, o.history, wrow), step, 0.0, kkt);
+    h = run_chunks<double, double>(pb, I, VAR_FP64, bufs_of(I, I.w64, o.history, wrow, false, o.restart), step,
+                                   0.0, kkt);
   refine_iters = h.iter - mixed_iters;
   out = h;
 }
@@ -773,7 +781,7 @@ void run_fp32(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double st
   }
   ensure_work<float>(A, I, I.w32, I.P32);
   HIPCHK(launch_convert_pad<double, float>(I.w64.X[0], I.w32.X[0], (long long)M, (int)Np, (int)Np, (int)Np, s));
-  Bufs<float> b32 = bufs_of(I, I.w32, o.history, wrow);
+  Bufs<float> b32 = bufs_of(I, I.w32, o.history, wrow, false, o.restart);
   start_from_x0<float>(pb, I, b32, VAR_FP32, kkt);
   SolverState h = run_chunks<float, float>(pb, I, VAR_FP32, b32, step, o.skip_refine ? 0.0 : kStallFp32, kkt);
   HIPCHK(launch_convert_pad<float, double>(I.w32.X[h.ix_cur], I.w64.X[0], (long long)M, (int)Np, (int)Np, (int)Np,
@@ -785,7 +793,7 @@ void run_fp32(pdt_problem_s* pb, Instance& I, const pdt_solve_opts& o, double st
     HIPCHK(launch_project_rows<double>(I.w64.X[0], I.w64.X[0], (long long)M, (int)I.N, (int)Np, (int)Np, s));
     // every FP32-phase stop is provisional: the FP64 start re-tests it on exact values
     write_state(s, I.st, restart_state(h));
-    Bufs<double> b64 = bufs_of(I, I.w64, o.history, wrow);
+    Bufs<double> b64 = bufs_of(I, I.w64, o.history, wrow, false, o.restart);
     start_from_x0<double>(pb, I, b64, VAR_FP64, kkt);
     h = run_chunks<double, double>(pb, I, VAR_FP64, b64, step, 0.0, kkt);
     if (h.ix_cur != 0)
@@ -1397,6 +1405,8 @@ pdt_status pdt_solve(pdt_problem_t pb, double* Pi, const pdt_solve_opts* opts, p
   if (!std::isfinite(o.kkt_tol) || o.kkt_tol < 0) return set_err(PDT_ERR_INVALID_ARG, "kkt_tol must be finite and >= 0");
   if (o.history_stride < 0) return set_err(PDT_ERR_INVALID_ARG, "history_stride must be >= 0");
   if (o.scaling != PDT_STEP_UNIFORM && o.scaling != PDT_STEP_DIAG) return set_err(PDT_ERR_INVALID_ARG, "bad scaling");
+  if (o.restart != PDT_RESTART_FUNCTION && o.restart != PDT_RESTART_GRADIENT)
+    return set_err(PDT_ERR_INVALID_ARG, "bad restart");
   const auto t0 = std::chrono::steady_clock::now();
   try {
     Instance& I = pb->inst[0];
@@ -1423,7 +1433,7 @@ pdt_status pdt_solve(pdt_problem_t pb, double* Pi, const pdt_solve_opts* opts, p
     SolverState fin;
     int64_t refine_iters = 0;
     if (o.precision == PDT_FP64) {
-      Bufs<double> b = bufs_of(I, I.w64, o.history, wrow);
+      Bufs<double> b = bufs_of(I, I.w64, o.history, wrow, false, o.restart);
       start_from_x0<double>(pb, I, b, VAR_FP64, o.kkt_tol > 0);
       fin = run_chunks<double, double>(pb, I, VAR_FP64, b, step, 0.0, o.kkt_tol > 0);
     } else if (o.precision == PDT_MIXED) {
@@ -1829,11 +1839,11 @@ template <typename T>
 constexpr int plan_slot() { return std::is_same<T, float>::value ? 1 : 0; }
 
 template <typename T>
-void build_plan(pdt_problem_s* pb, int scaling, const std::vector<double>& steps) {
+void build_plan(pdt_problem_s* pb, int scaling, int restart, const std::vector<double>& steps) {
   const int prec = std::is_same<T, float>::value ? PDT_FP32 : PDT_FP64;
   BatchPlan& P = pb->plan[plan_slot<T>()];
   Arena& PA = pb->plan_arena[plan_slot<T>()];
-  if (P.prec == prec && P.scaling == scaling && P.steps == steps) return;
+  if (P.prec == prec && P.scaling == scaling && P.restart == restart && P.steps == steps) return;
   if (P.graph) (void)hipGraphExecDestroy(P.graph);
   P = BatchPlan();
   PA.release();
@@ -1851,7 +1861,7 @@ void build_plan(pdt_problem_s* pb, int scaling, const std::vector<double>& steps
     BatchInst<T> bi;
     bi.pv = view_var(I, var);
     bi.pv.fx_split = 1;  // batches run one workgroup per probe tile
-    bi.b = bufs_of(I, work_of<T>(I), nullptr, scaling == PDT_STEP_DIAG ? I.wrow : nullptr);
+    bi.b = bufs_of(I, work_of<T>(I), nullptr, scaling == PDT_STEP_DIAG ? I.wrow : nullptr, false, restart);
     bi.b.fx_part = nullptr;
     bi.b.fx_count = nullptr;
     bi.st = I.st;
@@ -1897,6 +1907,7 @@ void build_plan(pdt_problem_s* pb, int scaling, const std::vector<double>& steps
   HIPCHK(hipStreamSynchronize(s));
   P.prec = prec;
   P.scaling = scaling;
+  P.restart = restart;
   P.steps = steps;
 }
 
@@ -1998,6 +2009,8 @@ pdt_status pdt_solve_batch(pdt_problem_t pb, double* const* Pi, const pdt_solve_
   if (o.history) return set_err(PDT_ERR_INVALID_ARG, "history is not supported for batches");
   if (o.kkt_tol != 0.0) return set_err(PDT_ERR_INVALID_ARG, "kkt_tol is not supported for batches");
   if (o.scaling != PDT_STEP_UNIFORM && o.scaling != PDT_STEP_DIAG) return set_err(PDT_ERR_INVALID_ARG, "bad scaling");
+  if (o.restart != PDT_RESTART_FUNCTION && o.restart != PDT_RESTART_GRADIENT)
+    return set_err(PDT_ERR_INVALID_ARG, "bad restart");
   for (size_t k = 0; k < n; ++k)
     if (!Pi[k]) return set_err(PDT_ERR_INVALID_ARG, "Pi[k] must not be NULL");
   const auto t0 = std::chrono::steady_clock::now();
@@ -2035,10 +2048,10 @@ pdt_status pdt_solve_batch(pdt_problem_t pb, double* const* Pi, const pdt_solve_
     std::vector<SolverState> fin, fin32;
     bool refined = false;
     if (o.precision == PDT_FP64) {
-      build_plan<double>(pb, o.scaling, steps);
+      build_plan<double>(pb, o.scaling, o.restart, steps);
       run_batch<double>(pb, 0.0, fin);
     } else {
-      build_plan<float>(pb, o.scaling, steps);
+      build_plan<float>(pb, o.scaling, o.restart, steps);
       run_batch<float>(pb, o.skip_refine ? 0.0 : kStallFp32, fin32);
       // the promoted FP32 iterates, in X64[0]
       for (size_t k = 0; k < n; ++k) {
@@ -2066,7 +2079,7 @@ pdt_status pdt_solve_batch(pdt_problem_t pb, double* const* Pi, const pdt_solve_
           HIPCHK(hipMemcpyAsync(pb->inst[k].st, &restart[k], sizeof(SolverState), hipMemcpyHostToDevice, s));
         }
         HIPCHK(hipStreamSynchronize(s));
-        build_plan<double>(pb, o.scaling, steps);
+        build_plan<double>(pb, o.scaling, o.restart, steps);
         run_batch<double>(pb, 0.0, fin);
         refined = true;
       }

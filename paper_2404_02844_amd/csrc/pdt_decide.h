@@ -57,11 +57,23 @@ __device__ __forceinline__ double first256_sum(double v, double* sh) {
 
 // Run by every thread of one block of BS threads (BS = 256, or the forward product's
 // workgroup when it takes the decision itself); the first 256 threads sum the partials.
+// Gradient-restart test of the step just taken (O'Donoghue and Candes): the sum of the
+// step's per-tile partials of sum_m (1 / w_m) sum_n (Y - X_new)(X_new - X_cur), added in
+// one fixed order by every block that needs it (the forward product, for the residual it
+// hands the next step, and the decision), so they all take the same decision.
+template <int BS>
+__device__ __forceinline__ bool restart_test(const double* rpart, int nr) {
+  __shared__ double shr[256];
+  const double s = threadIdx.x < 256 ? strided_sum256(rpart, nr, threadIdx.x) : 0.0;
+  return first256_sum<BS>(s, shr) > 0.0;
+}
+
 template <int BS>
 __device__ __forceinline__ void decide_body(const double* partials, int n, SolverState* st, double* history,
-                                            int mode) {
+                                            int mode, const double* rpart = nullptr, int nr = 0) {
   __shared__ double sh[256];
   if ((mode == DEC_ITER || mode == DEC_RESYNC) && st->done) return;
+  const bool reset = (mode == DEC_ITER && rpart) ? restart_test<BS>(rpart, nr) : false;
   const double s = threadIdx.x < 256 ? strided_sum256(partials, n, threadIdx.x) : 0.0;
   const double f = first256_sum<BS>(s, sh);
   if (mode == DEC_KKT) {
@@ -118,7 +130,7 @@ __device__ __forceinline__ void decide_body(const double* partials, int n, Solve
     st->ix_new = 3 - c - nw;
     st->f_cur = f;
     st->sel_acc = 1;
-    tt = tn;
+    tt = reset ? 1.0 : tn;
   } else {
     st->ix_prev = st->ix_cur;
     st->sel_acc = 0;

@@ -100,6 +100,8 @@ struct Bufs {
   unsigned* fx_count = nullptr;  // [tiles] finished workgroups per tile, zero between launches
   const int* skip = nullptr;     // when set and *skip != 0 the launch returns at once (the
                                  // Hessian products of a conjugate-gradient solve that stopped)
+  double* rpart = nullptr;       // [ceil(M / 16)] gradient-restart partials, one per row tile,
+                                 // written by the step (null: function restart only)
   float* R32_acc = nullptr;      // [D][Npad] FP32 copies of R_acc / R_rej (mixed path): every
   float* R32_rej = nullptr;      // forward-product epilogue that writes R writes them too, and
                                  // the FP32-operand transposed product reads them instead of R
@@ -124,8 +126,9 @@ hipError_t launch_fx(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int
 template <typename TS, typename TC = TS>
 hipError_t launch_ftr(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode, double step,
                       hipStream_t s);
+// rpart / nr: the step's gradient-restart partials (DEC_ITER; null: function restart only)
 hipError_t launch_decide(const double* partials, int n, SolverState* st, double* history, int mode,
-                         hipStream_t s);
+                         hipStream_t s, const double* rpart = nullptr, int nr = 0);
 hipError_t launch_setup_bands(const double* mu, int D, int M, double tau, int lump, int* lo, int* hi,
                               double* tail, hipStream_t s);
 hipError_t launch_fill_rinv(double* rinv, double* r4, int n, hipStream_t s);

@@ -20,14 +20,14 @@ namespace pdt {
 // Fixed-order reduction of the partials and the accept/reject decision.
 // ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void decide_kernel(const double* partials, int n, SolverState* st,
-                                                     double* history, int mode) {
-  decide_body<256>(partials, n, st, history, mode);
+                                                     double* history, int mode, const double* rpart, int nr) {
+  decide_body<256>(partials, n, st, history, mode, rpart, nr);
 }
 
 template <typename TS>
 __global__ __launch_bounds__(256) void decide_batch_kernel(const BatchInst<TS>* insts, int mode) {
   const BatchInst<TS>& I = insts[blockIdx.x];
-  decide_body<256>(I.b.partials, I.n_dt, I.st, I.b.history, mode);
+  decide_body<256>(I.b.partials, I.n_dt, I.st, I.b.history, mode, I.b.rpart, I.n_mt);
 }
 
 // Batches: every instance's state into one array (one copy to the host per chunk), and
@@ -256,8 +256,8 @@ template hipError_t launch_decide_batch<double>(const BatchInst<double>*, int, i
 template hipError_t launch_decide_batch<float>(const BatchInst<float>*, int, int, hipStream_t);
 
 hipError_t launch_decide(const double* partials, int n, SolverState* st, double* history, int mode,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(256), 0, s, partials, n, st, history, mode);
+                         hipStream_t s, const double* rpart, int nr) {
+  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(256), 0, s, partials, n, st, history, mode, rpart, nr);
   return hipGetLastError();
 }
 

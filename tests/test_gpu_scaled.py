@@ -176,3 +176,64 @@ def test_scaled_kkt_certificate_small(dev):
     pb.solve(Pi, max_iters=20000, scaling=_pdt.PDT_STEP_DIAG)
     k2 = certify.kkt_residual(F, inst.P, Pi.cpu().numpy(), inst.gamma)
     assert k2 < 1e-2 * k1
+
+
+# ---- gradient restart (O'Donoghue and Candes) ----------------------------------------------
+
+@pytest.mark.parametrize("which,iters,scaled", [("c1", 2000, True), ("c1", 2000, False), ("small", 600, True),
+                                                ("ragged", 600, True)])
+def test_gradient_restart_trajectory(dev, which, iters, scaled):
+    # the same iteration as the oracle's, with its momentum resets at the same steps
+    inst = INSTANCES[which]()
+    F, w, Lw = oracle_scaling(inst)
+    L = Lw if scaled else fista.lipschitz(F, inst.gamma, inst.M)
+    ref = fista.fista_r(F, inst.P, inst.gamma, L, iters, exact_sums=False, row_w=w if scaled else None,
+                        restart="gradient")
+    plain = fista.fista_r(F, inst.P, inst.gamma, L, iters, exact_sums=False, row_w=w if scaled else None)
+    assert np.any(ref.history != plain.history)  # the restarts change the trajectory
+    pb = _pdt.Problem.from_instance(inst)
+    for prec, fbar, xbar in ((_pdt.PDT_FP64, 1e-9, 1e-6), (_pdt.PDT_MIXED, 1e-4, 1e-4)):
+        Pi = torch.zeros((inst.M, inst.N), dtype=torch.float64, device=dev)
+        hist = torch.zeros(iters, dtype=torch.float64, device=dev)
+        info = pb.solve(Pi, precision=prec, max_iters=iters, step_L=L, history=hist,
+                        scaling=_pdt.PDT_STEP_DIAG if scaled else _pdt.PDT_STEP_UNIFORM,
+                        restart=_pdt.PDT_RESTART_GRADIENT)
+        assert info["iters"] == iters
+        assert abs(info["objective"] - ref.f) <= fbar * ref.f, prec
+        assert np.max(np.abs(Pi.cpu().numpy() - ref.X)) <= xbar, prec
+        if prec == _pdt.PDT_FP64:
+            assert np.max(np.abs(hist.cpu().numpy() - ref.history) / ref.history) < 1e-9
+
+
+def test_gradient_restart_optimum_c2(dev):
+    # the restarted solve reaches the oracle's stored optimum (tests/golden/c2_oracle.json)
+    with open(os.path.join(GOLDEN, "c2_oracle.json")) as fh:
+        gold = json.load(fh)
+    inst = synth.c2_medium()
+    pb = _pdt.Problem.from_instance(inst)
+    fstar = gold["f_star"]
+    for prec in (_pdt.PDT_FP64, _pdt.PDT_MIXED, _pdt.PDT_FP32):
+        Pi = torch.zeros((inst.M, inst.N), dtype=torch.float64, device=dev)
+        info = pb.solve(Pi, precision=prec, max_iters=40000, rel_obj_tol=1e-9, f_star=fstar,
+                        scaling=_pdt.PDT_STEP_DIAG, restart=_pdt.PDT_RESTART_GRADIENT)
+        print(f"[restart] M=4096 precision {prec}: iters {info['iters']} refine {info['refine_iters']}", flush=True)
+        assert info["converged"] == 1 and (info["objective"] - fstar) <= 1e-9 * fstar
+        d = np.max(np.abs(Pi.cpu().numpy()[:: gold["row_step"]] - np.array(gold["Pi_star"]["rows"])))
+        assert d <= 1e-4
+
+
+@pytest.mark.parametrize("precision", [_pdt.PDT_FP64, _pdt.PDT_FP32])
+def test_gradient_restart_batch_equals_single(dev, precision):
+    insts = [small_instance(M=m, B=b, D=d, mu_max=1.1 * m, seed=s) for m, b, d, s in
+             ((200, 20, 240, 1), (333, 9, 400, 2), (120, 40, 144, 3))]
+    bp = _pdt.BatchProblem(insts)
+    Pis = [torch.zeros((i.M, i.N), dtype=torch.float64, device=dev) for i in insts]
+    infos = bp.solve(Pis, precision=precision, max_iters=700, scaling=_pdt.PDT_STEP_DIAG,
+                     restart=_pdt.PDT_RESTART_GRADIENT)
+    for inst, Pi, info in zip(insts, Pis, infos):
+        pb = _pdt.Problem.from_instance(inst)
+        X = torch.zeros_like(Pi)
+        single = pb.solve(X, precision=precision, max_iters=700, scaling=_pdt.PDT_STEP_DIAG,
+                          restart=_pdt.PDT_RESTART_GRADIENT)
+        assert info["iters"] == single["iters"] and info["refine_iters"] == single["refine_iters"]
+        assert torch.equal(Pi, X)

@@ -407,9 +407,12 @@ def bench_c5(args):
     log(f"[bench] generated {n_test} unseen detectors of the M=16384 family in {time.perf_counter() - t0:.1f} s")
     model = warmstart.load_model()
     meta = warmstart.load_params()[2]
+    if args.kernels_only:
+        return c5_kernels_only(tests[0], model)
     DIAG, UNIFORM = _pdt.PDT_STEP_DIAG, _pdt.PDT_STEP_UNIFORM
     COLD, LEARNED = _pdt.PDT_INIT_UNIFORM, _pdt.PDT_INIT_LEARNED
     FP64, MIXED = _pdt.PDT_FP64, _pdt.PDT_MIXED
+    GRAD, FUNC = _pdt.PDT_RESTART_GRADIENT, _pdt.PDT_RESTART_FUNCTION
     rows = []
     headline = None
     for k, inst in enumerate(tests):
@@ -418,16 +421,16 @@ def bench_c5(args):
         Pi = torch.zeros((M, N), dtype=torch.float64, device="cuda")
         pb.solve(Pi, max_iters=0, scaling=DIAG)  # set-up of the row-scaled step's L_w (untimed)
         t = time.perf_counter()
-        ref = pb.solve(Pi, max_iters=60000, kkt_tol=1e-13, scaling=DIAG)
+        ref = pb.solve(Pi, precision=MIXED, max_iters=40000, kkt_tol=1e-12, scaling=DIAG, restart=GRAD)
         f_ref = ref["objective"]
         log(f"[bench] detector {k} (bins {inst.detector['B']}): reference f={f_ref:.16e} kkt={ref['kkt']:.2e} "
             f"iters={ref['iters']} ({time.perf_counter() - t:.1f} s)")
 
-        def solve(init, prec, scaling=DIAG, max_iters=60000):
+        def solve(init, prec, scaling=DIAG, max_iters=60000, restart=GRAD):
             torch.cuda.synchronize()
             t = time.perf_counter()
             info = pb.solve(Pi, init=init, precision=prec, max_iters=max_iters, rel_obj_tol=args.tol, f_star=f_ref,
-                            scaling=scaling, model=model if init == LEARNED else None)
+                            scaling=scaling, model=model if init == LEARNED else None, restart=restart)
             torch.cuda.synchronize()
             info["wall"] = time.perf_counter() - t
             info["relobj"] = (info["objective"] - f_ref) / f_ref
@@ -448,18 +451,21 @@ def bench_c5(args):
             headline = {"elapsed": elapsed, "iters": sum(r["iters"] for r in timed), "runs": timed,
                         "M": M, "N": N, "D": inst.D, "nnz": pb.bands()["nnz"], "pb": pb}
             row["warm_mixed"] = timed[len(timed) // 2]
-            plan = [("cold_fp64_uniform", COLD, FP64, UNIFORM, args.uniform_iters)]
+            # the plain method: uniform step 1/L, function restart only
+            plan = [("cold_fp64_uniform", COLD, FP64, UNIFORM, args.uniform_iters, FUNC),
+                    ("cold_fp64_function", COLD, FP64, DIAG, 60000, FUNC)]
         else:
-            plan = [("warm_mixed", LEARNED, MIXED, DIAG, 60000)]
-        plan += [("cold_fp64", COLD, FP64, DIAG, 60000), ("warm_fp64", LEARNED, FP64, DIAG, 60000),
-                 ("cold_mixed", COLD, MIXED, DIAG, 60000)]
-        for name, init, prec, sc, mi in plan:
-            row[name] = solve(init, prec, sc, mi)
+            plan = [("warm_mixed", LEARNED, MIXED, DIAG, 60000, GRAD)]
+        plan += [("cold_fp64", COLD, FP64, DIAG, 60000, GRAD), ("warm_fp64", LEARNED, FP64, DIAG, 60000, GRAD),
+                 ("cold_mixed", COLD, MIXED, DIAG, 60000, GRAD)]
+        for name, init, prec, sc, mi, rs in plan:
+            row[name] = solve(init, prec, sc, mi, rs)
         # the start itself: its objective against 1/N, and the cost of forming it
         Pi.zero_()
         row["f_start_learned"] = pb.solve(Pi, init=LEARNED, model=model, max_iters=0)["objective"]
         row["f_start_cold"] = pb.solve(Pi, max_iters=0)["objective"]
-        for name in ("cold_fp64_uniform", "cold_fp64", "warm_fp64", "cold_mixed", "warm_mixed"):
+        for name in ("cold_fp64_uniform", "cold_fp64_function", "cold_fp64", "warm_fp64", "cold_mixed",
+                     "warm_mixed"):
             if name in row:
                 r = row[name]
                 row[name] = {"time_s": r["wall"], "iters": int(r["iters"]), "refine_iters": int(r["refine_iters"]),
@@ -467,7 +473,8 @@ def bench_c5(args):
                              "fell_back_to_cold": int(r["fell_back_to_cold"])}
         log(f"[bench] detector {k}: " + ", ".join(
             f"{n} {row[n]['iters']} it {row[n]['time_s']:.2f} s" for n in
-            ("cold_fp64_uniform", "cold_fp64", "warm_fp64", "cold_mixed", "warm_mixed") if n in row))
+            ("cold_fp64_uniform", "cold_fp64_function", "cold_fp64", "warm_fp64", "cold_mixed", "warm_mixed")
+            if n in row))
         rows.append(row)
         if k > 0:
             pb.close()
@@ -491,6 +498,7 @@ def bench_c5(args):
                 "fp64_ftr_frac_of_fp64_peak": flops / times["ftr"] / 1e12 / PEAK_FP64_TFLOPS}
     h0 = rows[0]
     speedup = {"vs_cold_fp64_scaled": h0["cold_fp64"]["time_s"] / h0["warm_mixed"]["time_s"],
+               "vs_cold_fp64_scaled_function_restart": h0["cold_fp64_function"]["time_s"] / h0["warm_mixed"]["time_s"],
                "vs_cold_fp64_uniform_lower_bound": h0["cold_fp64_uniform"]["time_s"] / h0["warm_mixed"]["time_s"],
                "network_alone_fp64": h0["cold_fp64"]["time_s"] / h0["warm_fp64"]["time_s"],
                "network_alone_mixed": h0["cold_mixed"]["time_s"] / h0["warm_mixed"]["time_s"]}
@@ -530,11 +538,14 @@ def bench_c5(args):
                    "pmf_threshold": 1e-16, "tail": "lump", "tolerance": args.tol, "band_entries": nnz,
                    "start": "learned (stored network, BF16 products)", "precision": "mixed (FP32 products, FP64 "
                    "iterates, objective and refinement)", "step": "row-scaled (Hessian diagonal)",
+                   "restart": "gradient (O'Donoghue-Candes) with the monotone reject",
                    "test_detector": "seed stream 6, index 0 (unseen in training)"},
         "time_to_tol_s": float(np.median([r["wall"] for r in warm_runs])),
         "iters_to_tol": int(np.median([r["iters"] for r in warm_runs])),
         "f_ref": rows[0]["f_ref"], "f_ref_kkt": rows[0]["f_ref_kkt"],
-        "plain_fp64": {"uniform_step": rows[0]["cold_fp64_uniform"], "row_scaled": rows[0]["cold_fp64"]},
+        "plain_fp64": {"uniform_step_function_restart": rows[0]["cold_fp64_uniform"],
+                       "row_scaled_function_restart": rows[0]["cold_fp64_function"],
+                       "row_scaled_gradient_restart": rows[0]["cold_fp64"]},
         "warm_fp64": rows[0]["warm_fp64"], "cold_mixed": rows[0]["cold_mixed"],
         "f_start": {"learned": rows[0]["f_start_learned"], "cold": rows[0]["f_start_cold"]},
         "speedup": speedup,
@@ -546,6 +557,28 @@ def bench_c5(args):
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def c5_kernels_only(inst, model):
+    """A short run for profilers on the M=16384 detector: 64 iterations in FP64 and in
+    mixed precision (warm start, row-scaled step, gradient restart), then 200 launches of
+    each kernel of the iteration, and a 256 MiB device copy that calibrates the HBM byte
+    counters."""
+    import torch
+    from paper_2404_02844_amd import _pdt
+    pb = _pdt.Problem.from_instance(inst)
+    Pi = torch.zeros((inst.M, inst.N), dtype=torch.float64, device="cuda")
+    for prec in (_pdt.PDT_FP64, _pdt.PDT_MIXED):
+        pb.solve(Pi, init=_pdt.PDT_INIT_LEARNED, model=model, precision=prec, max_iters=64,
+                 scaling=_pdt.PDT_STEP_DIAG, restart=_pdt.PDT_RESTART_GRADIENT)
+        for kern in (0, 1, 2):
+            _pdt.pdt_replay_kernel(pb.handle, kern, prec, 200)
+    src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("[bench] c5 kernels-only pass done")
 
 
 def _gen_c4(i):

@@ -346,3 +346,15 @@ def c4_batch(count: int = 256, m_range=(256, 8192)) -> list[Instance]:
         M = int(rng.integers(m_range[0], m_range[1] + 1))
         out.append(random_detector(rng, M, name=f"c4_{i}"))
     return out
+
+
+def fidelity_columns(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Eq. fidelities for diagonal POVM elements, one value per outcome column:
+    (sum_i sqrt(a_i b_i))^2 / (sum_i a_i sum_i b_i) (scoring of a reconstruction against
+    a known synthetic POVM; not part of the solver)."""
+    num = np.sum(np.sqrt(np.clip(A, 0, None) * np.clip(B, 0, None)), axis=0) ** 2
+    den = A.sum(axis=0) * B.sum(axis=0)
+    out = np.ones(A.shape[1])
+    ok = den > 0
+    out[ok] = num[ok] / den[ok]
+    return out

@@ -283,6 +283,21 @@ pdt_status pdt_problem_set_fx_split(pdt_problem_t problem, int64_t instance, int
 pdt_status pdt_problem_fx_split(pdt_problem_t problem, int64_t instance, int* split);
 
 /*
+ * Split contraction of the transposed band product F^T R (a launch parameter, not a
+ * quantity of the paper).  Each 16-row tile's probe range (its 64-probe chunks) is cut
+ * into `split` contiguous parts, one workgroup each, whose partial tiles a second
+ * launch sums in part order before the projected step.  More workgroups fill
+ * the GPU when row tiles are few against their probe ranges (M = 4096 rows: 256 tiles of
+ * ~760 probes).  split in [1, 16], or 0 for the automatic choice made at setup (1).
+ * Scratch: [ceil(M/16) * split * 16 * Npad] FP64, allocated on first use and kept.
+ * Batched solves always run one workgroup per row tile.  Different splits differ in
+ * rounding only.  Drops captured graphs.
+ */
+pdt_status pdt_problem_set_ftr_split(pdt_problem_t problem, int64_t instance, int split);
+/* The split in effect (host int*). */
+pdt_status pdt_problem_ftr_split(pdt_problem_t problem, int64_t instance, int* split);
+
+/*
  * The paper's own solver: the two-stage two-metric projected truncated Newton method
  * of App. B (Algorithms 1-3) on instance 0.
  *
@@ -314,7 +329,8 @@ pdt_status pdt_problem_fx_split(pdt_problem_t problem, int64_t instance, int* sp
  * FP64 arrays, N padded to a multiple of 16, and a byte mask), two ints of pinned host memory mapped for the device (the CG
  * completion flags) and, on the first CG solve of each stage, two recorded graphs of
  * four CG iterations.  The problem keeps all of them until pdt_destroy_problem;
- * pdt_problem_set_tiles and pdt_problem_set_fx_split drop the graphs.
+ * pdt_problem_set_tiles, pdt_problem_set_fx_split and pdt_problem_set_ftr_split drop
+ * the graphs.
  */
 typedef struct {
   int64_t max_newton;     /* Newton steps of both stages, >= 0 */

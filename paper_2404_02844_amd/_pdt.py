@@ -115,6 +115,10 @@ def lib() -> ctypes.CDLL:
         L.pdt_problem_fx_split.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_int)]
         L.pdt_problem_set_fx_split.restype = ctypes.c_int
         L.pdt_problem_fx_split.restype = ctypes.c_int
+        L.pdt_problem_set_ftr_split.argtypes = [vp, i64, ctypes.c_int]
+        L.pdt_problem_ftr_split.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_int)]
+        L.pdt_problem_set_ftr_split.restype = ctypes.c_int
+        L.pdt_problem_ftr_split.restype = ctypes.c_int
         L.pdt_replay_kernel.restype = ctypes.c_int
         L.pdt_model_create.argtypes = [i64, i64, i64, vp, vp, ctypes.POINTER(vp)]
         L.pdt_model_destroy.argtypes = [vp]
@@ -396,6 +400,14 @@ class Problem:
     def fx_split(self):
         v = ctypes.c_int()
         _check(lib().pdt_problem_fx_split(self.handle, 0, ctypes.byref(v)))
+        return v.value
+
+    def set_ftr_split(self, split):
+        _check(lib().pdt_problem_set_ftr_split(self.handle, 0, int(split)))
+
+    def ftr_split(self):
+        v = ctypes.c_int()
+        _check(lib().pdt_problem_ftr_split(self.handle, 0, ctypes.byref(v)))
         return v.value
 
     def close(self):

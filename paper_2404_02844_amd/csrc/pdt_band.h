@@ -332,18 +332,21 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
   }
   double part = 0.0;
   if (dval_e) {
+    if constexpr (!kHoist) {
+      // every column tile's loads are issued before the first store (which the compiler
+      // may not move them across)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const size_t off = (size_t)dd * Npad + nt * 16 + i;
+        hoc[nt] = iter ? Ocur[off] : (T)0;
+        hp[nt] = b.P[off];
+      }
+    }
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const int n = nt * 16 + i;
       const size_t off = (size_t)dd * Npad + n;
-      T oc_, pv_;
-      if constexpr (kHoist) {
-        oc_ = hoc[nt];
-        pv_ = hp[nt];
-      } else {
-        oc_ = iter ? Ocur[off] : (T)0;
-        pv_ = b.P[off];
-      }
+      const T oc_ = hoc[nt], pv_ = hp[nt];
       const T o = delta ? oc_ + (T)S[(4 * wv + kq) * LDT + n] : (T)S[(4 * wv + kq) * LDT + n];
       O[off] = o;
       if (n < N) {
@@ -399,12 +402,23 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
 // range in 64-probe chunks.  Per chunk a wave generates F[d][m0..m0+15] for its 64
 // probes (lane = probe, recursion along m) into its own LDS slice and reads it back
 // transposed as the MFMA A operand; the R rows of the next PF steps are prefetched.
+//
+// Split contraction (pv.ftr_split = S > 1, for row tiles whose probe ranges are long
+// against the number of tiles): two launches.  In the first (FTR_PART) workgroup wg
+// takes the contiguous part wg % S of tile wg / S's chunks and writes its partial tile;
+// in the second (FTR_FINISH) workgroup mt sums tile mt's S partial tiles in part order
+// and runs the epilogue.  (The kernel boundary publishes the partial tiles; a per-tile
+// handshake inside one launch would need a device-scope fence per workgroup, which
+// writes the XCD's L2 back each time.)
 // ---------------------------------------------------------------------------------------
 template <typename TS, typename TC, int NT, int KS>
 __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode,
-                                         double step, int mt) {
+                                         double step, int wg, int phase = FTR_FUSED) {
   if (mode == FTR_STEP && st->done) return;
   if (b.skip && *b.skip) return;
+  const int nsplit = phase == FTR_FUSED ? 1 : pv.ftr_split;
+  const int mt = phase == FTR_PART ? wg / nsplit : wg;
+  const int sidx = phase == FTR_PART ? wg - mt * nsplit : 0;
   typedef TS T;
   typedef typename Acc<TC>::type AccT;
   constexpr int LDT = 16 * NT + 1;
@@ -450,9 +464,11 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
       }
   };
   const int nchunks = dhi >= dlo ? (dhi - dlo) / kChunkD + 1 : 0;
-  // wave wv takes chunks wv, wv + KS, ...: its rounds end with its last nonempty chunk
-  // (chunks past dhi would only add exact zeros)
-  const int rounds = wv < nchunks ? (nchunks - wv + KS - 1) / KS : 0;
+  // this workgroup's part of the chunks: [cs0, cs1)
+  const int cs0 = (nchunks * sidx) / nsplit, ncs = (nchunks * (sidx + 1)) / nsplit - cs0;
+  // wave wv takes chunks cs0 + wv, cs0 + wv + KS, ...: its rounds end with its last
+  // nonempty chunk (chunks past dhi would only add exact zeros)
+  const int rounds = (phase != FTR_FINISH && wv < ncs) ? (ncs - wv + KS - 1) / KS : 0;
   constexpr int stride = kChunkD * KS;
   // the tile's 16 photon numbers are shared by every probe: 1/(m+1) once per workgroup
   double inv[16];
@@ -497,40 +513,96 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
   const T beta = (T)st->beta;
   const T* __restrict__ Xc = b.X[st->ix_cur];
   const T* __restrict__ Xp = b.X[st->ix_prev];
-  auto form_y = [&](int nt, T& xc, T& y, T& ly) {
-    const int n = nt * 16 + i;
-    xc = 0;
-    y = 0;
-    ly = 0;
-    if (mval && n < N) {
-      const size_t off = (size_t)m * Npad + n;
-      xc = Xc[off];
-      y = xc + beta * (xc - Xp[off]);
-      if (m > 0) {
-        const T xm = Xc[off - Npad];
-        ly += y - (xm + beta * (xm - Xp[off - Npad]));
-      }
-      if (m < M - 1) {
-        const T xq = Xc[off + Npad];
-        ly += y - (xq + beta * (xq - Xp[off + Npad]));
-      }
+  // All 6 NT loads (rows m-1, m, m+1 of both iterates; rows clamped into [0, M-1],
+  // padding columns read and discarded) are issued before any of them is used, so the
+  // group waits for memory once, not once per column tile.
+  auto form_y = [&](T (&xc)[NT], T (&y)[NT], T (&ly)[NT]) {
+    const int mc = m < M - 1 ? m : M - 1;
+    const size_t r0 = (size_t)mc * Npad + i;
+    const size_t rm = mc > 0 ? r0 - Npad : r0;
+    const size_t rq = mc < M - 1 ? r0 + Npad : r0;
+    T a[NT], ap[NT], am[NT], amp[NT], aq[NT], aqp[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      a[nt] = Xc[r0 + 16 * nt];
+      ap[nt] = Xp[r0 + 16 * nt];
+      am[nt] = Xc[rm + 16 * nt];
+      amp[nt] = Xp[rm + 16 * nt];
+      aq[nt] = Xc[rq + 16 * nt];
+      aqp[nt] = Xp[rq + 16 * nt];
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const bool v = mval && nt * 16 + i < N;
+      const T yy = a[nt] + beta * (a[nt] - ap[nt]);
+      const T lm = m > 0 ? yy - (am[nt] + beta * (am[nt] - amp[nt])) : (T)0;
+      const T lq = m < M - 1 ? yy - (aq[nt] + beta * (aq[nt] - aqp[nt])) : (T)0;
+      xc[nt] = v ? a[nt] : (T)0;
+      y[nt] = v ? yy : (T)0;
+      ly[nt] = v ? lm + lq : (T)0;
     }
   };
+  // (a split tile's epilogue runs in one of its workgroups, found only at the end)
   constexpr bool kHoist = NT >= 4 && NT <= 5;
+  const bool hoist = kHoist && phase == FTR_FUSED;
   T hx[NT], hy[NT], hly[NT];
   if constexpr (kHoist) {
-    if (mode == FTR_STEP) {
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) form_y(nt, hx[nt], hy[nt], hly[nt]);
-    }
+    if (mode == FTR_STEP && hoist) form_y(hx, hy, hly);
   }
+
+  // Narrow probe ranges (at most kNarrowD probes: the thin row tiles of sparse, wide
+  // bands, e.g. mu_d = d^2) skip the 64-probe chunks.  Contraction step q takes probes
+  // dlo + 4q .. dlo + 4q + 3 (one per 16-lane group) and goes to wave q % KS; each lane
+  // forms its own F[d][m0 + i] from the tile's anchor by the same recursion (the same
+  // products in the same order as the chunked generator), and the NT products of the
+  // step read R rows directly.  The waves' partial tiles are summed as below.
+  const bool narrow = phase == FTR_FUSED && dhi >= dlo && dhi - dlo < kNarrowD;
+  // (in the same column passes as the chunked contraction)
 #pragma unroll 1
-  for (int pass = 0; pass < NPASS; ++pass) {
+  for (int pass = 0; pass < (narrow ? NPASS : 0); ++pass) {
     const int nt0 = pass * NTC;
     AccT acc[NTC];
 #pragma unroll
     for (int k = 0; k < NTC; ++k) acc[k] = AccT{0, 0, 0, 0};
-    int dc = dlo + kChunkD * wv;
+    const int nks = (dhi - dlo) / 4 + 1;
+    const int mm = m0 + i;
+#pragma unroll 1
+    for (int q = wv; q < nks; q += KS) {
+      const int d = dlo + 4 * q + kq;
+      const int dr = d < dhi ? d : dhi;
+      TC rv[NTC];
+      const unsigned base = (unsigned)dr * (unsigned)Npad + (unsigned)i + 16u * (unsigned)nt0;
+#pragma unroll
+      for (int k = 0; k < NTC; ++k)
+        if (NPASS == 1 || nt0 + k < NT) {
+          if constexpr (kR32) rv[k] = (TC)R32[base + 16u * k];
+          else rv[k] = (TC)R[base + 16u * k];
+        }
+      double f = 0.0;
+      if (d <= dhi) {
+        const double mu = pv.mu[d];
+        const int blo = pv.lo[d], bhi = pv.hi[d];
+        double p = anc[d - dlo];
+#pragma unroll
+        for (int j = 0; j < 15; ++j) p = j < i ? p * (mu * inv[j]) : p;
+        const bool in = mm >= blo && mm <= bhi;
+        f = in ? p : 0.0;
+        if (mm == lumpm && in) f = pv.tail[d];
+      }
+      const TC a = (TC)f;
+#pragma unroll
+      for (int k = 0; k < NTC; ++k)
+        if (NPASS == 1 || nt0 + k < NT) acc[k] = Acc<TC>::mfma(a, rv[k], acc[k]);
+    }
+    reduce_tiles<TC, NTC, KS>(acc, S + 16 * nt0, LDT, wv, i, kq, NT - nt0);
+  }
+#pragma unroll 1
+  for (int pass = 0; pass < ((phase == FTR_FINISH || narrow) ? 0 : NPASS); ++pass) {
+    const int nt0 = pass * NTC;
+    AccT acc[NTC];
+#pragma unroll
+    for (int k = 0; k < NTC; ++k) acc[k] = AccT{0, 0, 0, 0};
+    int dc = dlo + kChunkD * (cs0 + wv);
     TC rb[PF][NTC];
 #pragma unroll
     for (int p = 0; p < PF; ++p) load_r(dc + 16 * kq + p, rb[p], nt0);
@@ -573,6 +645,22 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
     reduce_tiles<TC, NTC, KS>(acc, S + 16 * nt0, LDT, wv, i, kq, NT - nt0);
   }
 
+  constexpr int kTile = 16 * 16 * NT;
+  if (phase == FTR_PART) {
+    double* mine = b.ftr_part + (size_t)wg * kTile;
+    for (int q = tid; q < kTile; q += 64 * KS) mine[q] = S[(q / (16 * NT)) * LDT + q % (16 * NT)];
+    return;
+  }
+  if (phase == FTR_FINISH) {
+    const double* parts = b.ftr_part + (size_t)mt * nsplit * kTile;
+    for (int q = tid; q < kTile; q += 64 * KS) {
+      double v = 0.0;
+      for (int sp = 0; sp < nsplit; ++sp) v += parts[(size_t)sp * kTile + q];
+      S[(q / (16 * NT)) * LDT + q % (16 * NT)] = v;
+    }
+    __syncthreads();
+  }
+
   // epilogue: wave wv finishes rows m0 + 4 wv + kq (one row per 16-lane group)
   const T g2 = (T)(2.0 * pv.gamma);
   if (mode == FTR_STEP) {
@@ -583,17 +671,11 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
     constexpr bool delta = !std::is_same<TS, TC>::value;
     T z[1][NT];
     T xcs[NT], ys[NT];
+    if (!(kHoist && hoist)) form_y(hx, hy, hly);
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const int n = nt * 16 + i;
-      T xc, y, ly;
-      if constexpr (kHoist) {
-        xc = hx[nt];
-        y = hy[nt];
-        ly = hly[nt];
-      } else {
-        form_y(nt, xc, y, ly);
-      }
+      const T xc = hx[nt], y = hy[nt], ly = hly[nt];
       xcs[nt] = xc;
       ys[nt] = y;
       T zz = (n < N) ? (T)0 : neg_huge<T>();
@@ -633,17 +715,26 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
     double part = 0.0;
     T g[NT], x[NT];
     T gmin = FLT_MAX;
+    // rows m-1, m, m+1 of every column tile are loaded before any is used
+    const int mc = m < M - 1 ? m : M - 1;
+    const size_t r0 = (size_t)mc * Npad + i;
+    const size_t rm = mc > 0 ? r0 - Npad : r0;
+    const size_t rq = mc < M - 1 ? r0 + Npad : r0;
+    T a[NT], am[NT], aq[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      a[nt] = Xc[r0 + 16 * nt];
+      am[nt] = Xc[rm + 16 * nt];
+      aq[nt] = Xc[rq + 16 * nt];
+    }
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const int n = nt * 16 + i;
       g[nt] = 0;
       x[nt] = 0;
       if (mval && n < N) {
-        const size_t off = (size_t)m * Npad + n;
-        const T xc = Xc[off];
-        T lx = 0;
-        if (m > 0) lx += xc - Xc[off - Npad];
-        if (m < M - 1) lx += xc - Xc[off + Npad];
+        const T xc = a[nt];
+        const T lx = (m > 0 ? xc - am[nt] : (T)0) + (m < M - 1 ? xc - aq[nt] : (T)0);
         g[nt] = (T)2 * (T)S[(4 * wv + kq) * LDT + n] + g2 * lx;
         x[nt] = xc;
         gmin = fmin(gmin, g[nt]);
@@ -697,10 +788,12 @@ __global__ __launch_bounds__(64 * KS) __attribute__((amdgpu_waves_per_eu(2))) vo
   fx_body<TS, TC, NT, KS>(pv, b, st, mode, gridDim.x - 1 - blockIdx.x, gridDim.x);
 }
 
+// FP32 operands keep three waves per SIMD (the epilogue's batched loads would otherwise
+// raise the register peak of the mixed kernel past that)
 template <typename TS, typename TC, int NT, int KS>
-__global__ __launch_bounds__(64 * KS) void ftr_kernel(ProbView pv, Bufs<TS> b, SolverState* st, int mode,
-                                                       double step) {
-  ftr_body<TS, TC, NT, KS>(pv, b, st, mode, step, gridDim.x - 1 - blockIdx.x);
+__global__ __launch_bounds__(64 * KS, (sizeof(TC) == 4 && KS == 4) ? 3 : 1) void ftr_kernel(
+    ProbView pv, Bufs<TS> b, SolverState* st, int mode, double step, int phase) {
+  ftr_body<TS, TC, NT, KS>(pv, b, st, mode, step, gridDim.x - 1 - blockIdx.x, phase);
 }
 
 // Batched launches: one workgroup per (instance, tile) item of a work list; every
@@ -733,8 +826,15 @@ static void fx_go(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mo
 template <typename TS, typename TC, int NT, int KS>
 static void ftr_go(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode, double step,
                    hipStream_t s) {
-  hipLaunchKernelGGL((ftr_kernel<TS, TC, NT, KS>), dim3(ftr_num_waves(pv)), dim3(64 * KS), 0, s, pv, b, st, mode,
-                     step);
+  if (pv.ftr_split > 1) {
+    hipLaunchKernelGGL((ftr_kernel<TS, TC, NT, KS>), dim3(ftr_num_waves(pv) * pv.ftr_split), dim3(64 * KS), 0, s,
+                       pv, b, st, mode, step, (int)FTR_PART);
+    hipLaunchKernelGGL((ftr_kernel<TS, TC, NT, KS>), dim3(ftr_num_waves(pv)), dim3(64 * KS), 0, s, pv, b, st, mode,
+                       step, (int)FTR_FINISH);
+  } else {
+    hipLaunchKernelGGL((ftr_kernel<TS, TC, NT, KS>), dim3(ftr_num_waves(pv)), dim3(64 * KS), 0, s, pv, b, st, mode,
+                       step, (int)FTR_FUSED);
+  }
 }
 
 #define PDT_NT_SWITCH(NTV, CALL)                 \

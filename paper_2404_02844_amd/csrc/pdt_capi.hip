@@ -158,6 +158,11 @@ struct Instance {
   size_t fx_part_cap = 0;        // doubles allocated for fx_part
   double* fx_part = nullptr;
   unsigned* fx_count = nullptr;
+  // split contraction of the transposed product: workgroups per 16-row tile
+  int ftr_split = 1;
+  int ftr_split_auto = 1;
+  size_t ftr_part_cap = 0;       // doubles allocated for ftr_part
+  double* ftr_part = nullptr;
   NewtonWork nw;
 };
 
@@ -244,6 +249,7 @@ ProbView view_of(const Instance& I) {
   pv.lump = I.lump;
   pv.gamma = I.gamma;
   pv.fx_split = I.fx_split;
+  pv.ftr_split = I.ftr_split;
   return pv;
 }
 
@@ -273,6 +279,7 @@ Bufs<T> bufs_of(const Instance& I, const Work<T>& w, double* history, const doub
   }
   b.fx_part = I.fx_part;
   b.fx_count = I.fx_count;
+  b.ftr_part = I.ftr_part;
   b.P = w.P;
   b.R_acc = w.R_acc;
   b.R_rej = w.R_rej;
@@ -343,6 +350,19 @@ void set_fx_split(Arena& A, Instance& I, int split) {
     I.fx_part_cap = need;
   }
   I.fx_split = split;
+}
+
+constexpr int kMaxFtrSplit = 16;
+
+// Workgroups per 16-row tile of the transposed product (the same scratch rule).
+void set_ftr_split(Arena& A, Instance& I, int split) {
+  const size_t n_mt = (size_t)((I.M + 15) / 16);
+  const size_t need = split > 1 ? n_mt * (size_t)split * 16 * (size_t)I.Npad : 0;
+  if (need > I.ftr_part_cap) {
+    I.ftr_part = A.alloc<double>(need);
+    I.ftr_part_cap = need;
+  }
+  I.ftr_split = split;
 }
 
 // Power iteration for lambda_max(W^(1/2) (2 F^T F + 2 gamma L) W^(1/2)) with the band
@@ -490,6 +510,8 @@ void setup_instance(pdt_problem_s* pb, Instance& I, const pdt_problem_desc& d) {
   I.fx_count = A.alloc<unsigned>(n_dt);
   HIPCHK(hipMemsetAsync(I.fx_count, 0, n_dt * sizeof(unsigned), s));
   set_fx_split(A, I, I.fx_split_auto);
+  I.ftr_split_auto = 1;
+  set_ftr_split(A, I, I.ftr_split_auto);
   // room for the partials of any split up to kMaxFxSplit
   // and for the gradient launch's KKT and Frank-Wolfe partials (2 per row tile)
   I.n_partials = (int)std::max(n_dt * (kMaxFxSplit + 1), 2 * n_mt);
@@ -869,6 +891,7 @@ Bufs<double> nt_bufs(const Instance& I, const NewtonWork& nw, const double* X, d
   b.history = nullptr;
   b.fx_part = I.fx_part;
   b.fx_count = I.fx_count;
+  b.ftr_part = I.ftr_part;
   b.skip = skip;
   return b;
 }
@@ -1231,6 +1254,28 @@ pdt_status pdt_problem_fx_split(pdt_problem_t pb, int64_t instance, int* split) 
   if (!pb || !split) return set_err(PDT_ERR_INVALID_ARG, "problem and split must not be NULL");
   if (instance < 0 || instance >= (int64_t)pb->inst.size()) return set_err(PDT_ERR_INVALID_ARG, "bad instance");
   *split = pb->inst[(size_t)instance].fx_split;
+  return PDT_OK;
+}
+
+pdt_status pdt_problem_set_ftr_split(pdt_problem_t pb, int64_t instance, int split) {
+  if (!pb) return set_err(PDT_ERR_INVALID_ARG, "problem is NULL");
+  if (instance < 0 || instance >= (int64_t)pb->inst.size()) return set_err(PDT_ERR_INVALID_ARG, "bad instance");
+  if (split < 0 || split > kMaxFtrSplit) return set_err(PDT_ERR_INVALID_ARG, "split must be in [0, 16]");
+  try {
+    Instance& I = pb->inst[(size_t)instance];
+    HIPCHK(hipStreamSynchronize(pb->stream));
+    drop_graphs(I);  // captured launches carry the old grid
+    set_ftr_split(pb->arena, I, split == 0 ? I.ftr_split_auto : split);
+    return PDT_OK;
+  } catch (...) {
+    return status_of_current_exception();
+  }
+}
+
+pdt_status pdt_problem_ftr_split(pdt_problem_t pb, int64_t instance, int* split) {
+  if (!pb || !split) return set_err(PDT_ERR_INVALID_ARG, "problem and split must not be NULL");
+  if (instance < 0 || instance >= (int64_t)pb->inst.size()) return set_err(PDT_ERR_INVALID_ARG, "bad instance");
+  *split = pb->inst[(size_t)instance].ftr_split;
   return PDT_OK;
 }
 
@@ -1860,10 +1905,12 @@ void build_plan(pdt_problem_s* pb, int scaling, int restart, const std::vector<d
     Instance& I = pb->inst[k];
     BatchInst<T> bi;
     bi.pv = view_var(I, var);
-    bi.pv.fx_split = 1;  // batches run one workgroup per probe tile
+    bi.pv.fx_split = 1;  // batches run one workgroup per probe tile and per row tile
+    bi.pv.ftr_split = 1;
     bi.b = bufs_of(I, work_of<T>(I), nullptr, scaling == PDT_STEP_DIAG ? I.wrow : nullptr, false, restart);
     bi.b.fx_part = nullptr;
     bi.b.fx_count = nullptr;
+    bi.b.ftr_part = nullptr;
     bi.st = I.st;
     bi.step = steps[k];
     bi.n_dt = fx_num_tiles(bi.pv);

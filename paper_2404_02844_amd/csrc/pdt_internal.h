@@ -27,6 +27,7 @@ namespace pdt {
 constexpr int kTile = 16;         // MFMA tile edge
 constexpr int kChunkM = 64;       // photon numbers per forward-product chunk
 constexpr int kChunkD = 64;       // probes per transposed-product chunk
+constexpr int kNarrowD = 32;      // probe ranges up to this many probes skip the chunks
 constexpr int kMaxNT = 12;        // outcome columns up to 192
 constexpr int kWave = 64;
 
@@ -34,6 +35,9 @@ constexpr int kWave = 64;
 // of the mixed path (O, both residual candidates and f of X_cur made exact again)
 enum FxMode { FX_ITER = 0, FX_INIT = 1, FX_EVAL = 2, FX_DELTA = 3, FX_EVAL_PREV = 4, FX_RESYNC = 5 };
 enum FtrMode { FTR_STEP = 0, FTR_GRAD = 1 };
+// Phases of the transposed product: one fused launch, or (split contraction) a launch of
+// partial tiles followed by a launch that sums them and runs the epilogue.
+enum FtrPhase { FTR_FUSED = 0, FTR_PART = 1, FTR_FINISH = 2 };
 // DEC_KKT: the KKT residual and Frank-Wolfe gap of X_cur from a gradient launch's
 // partials ([n] KKT sums, then [n] gap sums), and the KKT stopping test
 enum DecideMode { DEC_ITER = 0, DEC_INIT = 1, DEC_EVAL = 2, DEC_RESYNC = 3, DEC_KKT = 4 };
@@ -80,6 +84,7 @@ struct ProbView {
   int ks_fx = 4;   // waves per workgroup of the forward product (4 or 8)
   int ks_ftr = 4;  // waves per workgroup of the transposed product (4 or 8)
   int fx_split = 1;  // workgroups sharing one 16-probe tile of the forward product
+  int ftr_split = 1;  // workgroups sharing one 16-row tile of the transposed product
 };
 
 template <typename T>
@@ -98,6 +103,8 @@ struct Bufs {
                                  // transposed product, read by the forward product)
   double* fx_part = nullptr;     // [tiles * fx_split][16][16 NT] partial tiles (split forward product)
   unsigned* fx_count = nullptr;  // [tiles] finished workgroups per tile, zero between launches
+  double* ftr_part = nullptr;    // [row tiles * ftr_split][16][16 NT] partial tiles (split
+                                 // transposed product)
   const int* skip = nullptr;     // when set and *skip != 0 the launch returns at once (the
                                  // Hessian products of a conjugate-gradient solve that stopped)
   double* rpart = nullptr;       // [ceil(M / 16)] gradient-restart partials, one per row tile,

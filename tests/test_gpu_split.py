@@ -1,9 +1,10 @@
-"""Split contraction of the forward band product (several workgroups per 16-probe tile,
-partial tiles summed in a fixed order by the last of them) against the FP64 oracle and
-against the unsplit launch, through the C ABI.
+"""Split contractions of the two band products (several workgroups per 16-probe tile of
+the forward product, or per 16-row tile of the transposed product, partial tiles summed
+in a fixed order by the last of them) against the FP64 oracle and against the unsplit
+launch, through the C ABI.
 
-Forced splits on small problems exercise every launch mode that goes through the
-forward product: the momentum iteration (FP64, FP32, mixed with its delta products and
+Forced splits on small problems exercise every launch mode that goes through the band
+products: the momentum iteration (FP64, FP32, mixed with its delta products and
 resyncs), plain evaluations, Newton-CG's Hessian products and objective evaluations.
 Tolerances as in the unsplit tests (the split changes only the order of the sums):
 trajectories 1e-9 relative f / 1e-6 max |dPi|; objective and gradient 1e-12; Newton
@@ -38,6 +39,8 @@ INSTANCES = {
     # few probes with wide bands: long photon-number ranges per probe tile
     "wideband": lambda: small_instance(M=3000, B=30, D=40, mu_max=2700.0, gamma=1e-4),
     "ragged": lambda: small_instance(M=37, B=4, D=23, mu_max=30.0),
+    # many probes per row: ~30 64-probe chunks per row tile of the transposed product
+    "denseband": lambda: small_instance(M=300, B=24, D=2000, mu_max=330.0, gamma=1e-4),
 }
 _cache = {}
 
@@ -50,14 +53,19 @@ def setup(which):
     return _cache[which]
 
 
+def set_split(pb, kind, split):
+    getattr(pb, f"set_{kind}_split")(split)
+    return getattr(pb, f"{kind}_split")()
+
+
+@pytest.mark.parametrize("kind", ["fx", "ftr"])
 @pytest.mark.parametrize("split", [2, 3, 8, 16])
 @pytest.mark.parametrize("which", list(INSTANCES))
-def test_split_trajectory_matches_oracle(dev, which, split):
+def test_split_trajectory_matches_oracle(dev, which, split, kind):
     inst, F, L = setup(which)
-    print(f"[split] {which} split {split}", flush=True)
+    print(f"[split] {kind} {which} split {split}", flush=True)
     pb = _pdt.Problem.from_instance(inst)
-    pb.set_fx_split(split)
-    assert pb.fx_split() == split
+    assert set_split(pb, kind, split) == split
     iters = 200
     ref = fista.fista_r(F, inst.P, inst.gamma, L, iters)
     Pi = torch.zeros((inst.M, inst.N), dtype=torch.float64, device=dev)
@@ -79,13 +87,14 @@ def test_split_trajectory_matches_oracle(dev, which, split):
     pb.close()
 
 
-@pytest.mark.parametrize("which", ["wideband", "small"])
-def test_split_is_deterministic_and_close_to_unsplit(dev, which):
+@pytest.mark.parametrize("kind,which", [("fx", "wideband"), ("fx", "small"), ("ftr", "denseband"),
+                                        ("ftr", "small")])
+def test_split_is_deterministic_and_close_to_unsplit(dev, which, kind):
     inst, F, L = setup(which)
     pb = _pdt.Problem.from_instance(inst)
     out = {}
     for split in (1, 4, 4):
-        pb.set_fx_split(split)
+        set_split(pb, kind, split)
         Pi = torch.zeros((inst.M, inst.N), dtype=torch.float64, device=dev)
         info = pb.solve(Pi, max_iters=300, scaling=_pdt.PDT_STEP_DIAG)
         out.setdefault(split, []).append((info["objective"], Pi.cpu().numpy()))
@@ -93,17 +102,18 @@ def test_split_is_deterministic_and_close_to_unsplit(dev, which):
     (fa, Xa), (fb, Xb) = out[4]
     assert fa == fb and np.array_equal(Xa, Xb)  # bit for bit
     assert abs(fa - f1) <= 1e-12 * f1 and np.max(np.abs(Xa - X1)) <= 1e-9
-    pb.set_fx_split(0)
+    set_split(pb, kind, 0)
     pb.close()
 
 
+@pytest.mark.parametrize("kind,which", [("fx", "wideband"), ("ftr", "denseband")])
 @pytest.mark.parametrize("precision,tol", [(_pdt.PDT_MIXED, 1e-4), (_pdt.PDT_FP32, 1e-3)])
-def test_split_reduced_precision_paths(dev, precision, tol):
-    inst, F, L = setup("wideband")
+def test_split_reduced_precision_paths(dev, precision, tol, kind, which):
+    inst, F, L = setup(which)
     pb = _pdt.Problem.from_instance(inst)
     res = {}
     for split in (1, 5):
-        pb.set_fx_split(split)
+        set_split(pb, kind, split)
         Pi = torch.zeros((inst.M, inst.N), dtype=torch.float64, device=dev)
         info = pb.solve(Pi, precision=precision, max_iters=400, scaling=_pdt.PDT_STEP_DIAG)
         res[split] = info["objective"]

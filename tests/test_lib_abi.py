@@ -69,6 +69,8 @@ def test_null_handles_are_rejected():
     assert L.pdt_hessian_apply(None, None, None) == _pdt.PDT_ERR_INVALID_ARG
     assert L.pdt_problem_set_fx_split(None, 0, 2) == _pdt.PDT_ERR_INVALID_ARG
     assert L.pdt_problem_fx_split(None, 0, None) == _pdt.PDT_ERR_INVALID_ARG
+    assert L.pdt_problem_set_ftr_split(None, 0, 2) == _pdt.PDT_ERR_INVALID_ARG
+    assert L.pdt_problem_ftr_split(None, 0, None) == _pdt.PDT_ERR_INVALID_ARG
     assert L.pdt_newton_direction(None, 1, None, 0.0, 1e-4, 10, None, None, None, None) == _pdt.PDT_ERR_INVALID_ARG
     L.pdt_destroy_problem(None)  # no-op
     assert "NULL" in _pdt.pdt_last_error()

@@ -411,7 +411,9 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
 // handshake inside one launch would need a device-scope fence per workgroup, which
 // writes the XCD's L2 back each time.)
 // ---------------------------------------------------------------------------------------
-template <typename TS, typename TC, int NT, int KS>
+// NW: every row tile of the problem has a narrow probe range (pv.ftr_narrow_all), so
+// the chunked contraction and its LDS staging are compiled out.
+template <typename TS, typename TC, int NT, int KS, bool NW = false>
 __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode,
                                          double step, int wg, int phase = FTR_FUSED) {
   if (mode == FTR_STEP && st->done) return;
@@ -430,7 +432,7 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
   constexpr int NPASS = (NT + NTC - 1) / NTC;
   // the F^T staging tiles of the main loop and the reduction tile share one LDS block
   // (a single pass), or sit side by side (two passes)
-  constexpr int kFt = KS * kChunkD * 17, kS = 16 * LDT;
+  constexpr int kFt = NW ? 0 : KS * kChunkD * 17, kS = 16 * LDT;
   __shared__ double lds[NPASS > 1 ? kFt + kS : (kFt > kS ? kFt : kS)];
   double(*Ft)[kChunkD][17] = reinterpret_cast<double(*)[kChunkD][17]>(lds);
   double* S = NPASS > 1 ? lds + kFt : lds;
@@ -556,7 +558,7 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
   // forms its own F[d][m0 + i] from the tile's anchor by the same recursion (the same
   // products in the same order as the chunked generator), and the NT products of the
   // step read R rows directly.  The waves' partial tiles are summed as below.
-  const bool narrow = phase == FTR_FUSED && dhi >= dlo && dhi - dlo < kNarrowD;
+  const bool narrow = phase == FTR_FUSED && (NW || (dhi >= dlo && dhi - dlo < kNarrowD));
   // (in the same column passes as the chunked contraction)
 #pragma unroll 1
   for (int pass = 0; pass < (narrow ? NPASS : 0); ++pass) {
@@ -564,7 +566,7 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
     AccT acc[NTC];
 #pragma unroll
     for (int k = 0; k < NTC; ++k) acc[k] = AccT{0, 0, 0, 0};
-    const int nks = (dhi - dlo) / 4 + 1;
+    const int nks = dhi >= dlo ? (dhi - dlo) / 4 + 1 : 0;
     const int mm = m0 + i;
 #pragma unroll 1
     for (int q = wv; q < nks; q += KS) {
@@ -597,7 +599,7 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
     reduce_tiles<TC, NTC, KS>(acc, S + 16 * nt0, LDT, wv, i, kq, NT - nt0);
   }
 #pragma unroll 1
-  for (int pass = 0; pass < ((phase == FTR_FINISH || narrow) ? 0 : NPASS); ++pass) {
+  for (int pass = 0; pass < ((NW || phase == FTR_FINISH || narrow) ? 0 : NPASS); ++pass) {
     const int nt0 = pass * NTC;
     AccT acc[NTC];
 #pragma unroll
@@ -796,6 +798,13 @@ __global__ __launch_bounds__(64 * KS, (sizeof(TC) == 4 && KS == 4) ? 3 : 1) void
   ftr_body<TS, TC, NT, KS>(pv, b, st, mode, step, gridDim.x - 1 - blockIdx.x, phase);
 }
 
+// every row tile narrow: no chunk staging, a smaller register and LDS footprint
+template <typename TS, typename TC, int NT>
+__global__ __launch_bounds__(256, NT <= 9 ? 4 : 3) void ftr_narrow_kernel(ProbView pv, Bufs<TS> b, SolverState* st, int mode,
+                                                          double step) {
+  ftr_body<TS, TC, NT, 4, true>(pv, b, st, mode, step, gridDim.x - 1 - blockIdx.x, FTR_FUSED);
+}
+
 // Batched launches: one workgroup per (instance, tile) item of a work list; every
 // instance carries its own problem view, buffers, state and step.
 template <typename TS, typename TC, int NT, int KS>
@@ -873,7 +882,13 @@ hipError_t launch_fx(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int
 template <typename TS, typename TC>
 hipError_t launch_ftr(const ProbView& pv, const Bufs<TS>& b, SolverState* st, int mode, double step,
                       hipStream_t s) {
-  if (pv.ks_ftr == 8) {
+  if (pv.ftr_narrow_all && pv.ftr_split == 1) {
+#define PDT_FTRN(K)                                                                                             \
+  hipLaunchKernelGGL((ftr_narrow_kernel<TS, TC, K>), dim3(ftr_num_waves(pv)), dim3(256), 0, s, pv, b, st, mode, \
+                     step)
+    PDT_NT_SWITCH(pv.Npad / 16, PDT_FTRN)
+#undef PDT_FTRN
+  } else if (pv.ks_ftr == 8) {
 #define PDT_FTR(K) ftr_go<TS, TC, K, 8>(pv, b, st, mode, step, s)
     PDT_NT_SWITCH(pv.Npad / 16, PDT_FTR)
 #undef PDT_FTR

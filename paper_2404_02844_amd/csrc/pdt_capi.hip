@@ -161,6 +161,7 @@ struct Instance {
   // split contraction of the transposed product: workgroups per 16-row tile
   int ftr_split = 1;
   int ftr_split_auto = 1;
+  int ftr_narrow_all = 0;  // every row tile's probe range is under kNarrowD probes
   size_t ftr_part_cap = 0;       // doubles allocated for ftr_part
   double* ftr_part = nullptr;
   NewtonWork nw;
@@ -250,6 +251,7 @@ ProbView view_of(const Instance& I) {
   pv.gamma = I.gamma;
   pv.fx_split = I.fx_split;
   pv.ftr_split = I.ftr_split;
+  pv.ftr_narrow_all = I.ftr_narrow_all;
   return pv;
 }
 
@@ -511,6 +513,9 @@ void setup_instance(pdt_problem_s* pb, Instance& I, const pdt_problem_desc& d) {
   HIPCHK(hipMemsetAsync(I.fx_count, 0, n_dt * sizeof(unsigned), s));
   set_fx_split(A, I, I.fx_split_auto);
   I.ftr_split_auto = 1;
+  I.ftr_narrow_all = 1;
+  for (size_t t = 0; t < n_mt; ++t)
+    if (mt_dhi[t] >= mt_dlo[t] && mt_dhi[t] - mt_dlo[t] >= kNarrowD) I.ftr_narrow_all = 0;
   set_ftr_split(A, I, I.ftr_split_auto);
   // room for the partials of any split up to kMaxFxSplit
   // and for the gradient launch's KKT and Frank-Wolfe partials (2 per row tile)

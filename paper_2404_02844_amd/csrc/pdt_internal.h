@@ -85,6 +85,7 @@ struct ProbView {
   int ks_ftr = 4;  // waves per workgroup of the transposed product (4 or 8)
   int fx_split = 1;  // workgroups sharing one 16-probe tile of the forward product
   int ftr_split = 1;  // workgroups sharing one 16-row tile of the transposed product
+  int ftr_narrow_all = 0;  // every row tile's probe range is narrow (under kNarrowD probes)
 };
 
 template <typename T>

@@ -274,8 +274,9 @@ pdt_status pdt_problem_tiles(pdt_problem_t problem, int64_t instance, int precis
  * the paper).  With few 16-probe tiles and long photon-number ranges (the paper's
  * experiment: D = 1076 probes with bands ~1.8e4 wide) each tile's contraction is shared
  * by `split` workgroups whose partial tiles the last of them sums in a fixed order.
- * split in [1, 16], or 0 for the automatic choice made at setup (up to 8 workgroups per
- * tile when there are fewer than 256 tiles, at least 32 64-entry chunks each; else 1).
+ * split in [1, 16], or 0 for the automatic choice made at setup (up to 16 workgroups
+ * per tile, about 768 in all, when there are fewer than 256 tiles, at least 32 64-entry
+ * chunks each; else 1).
  * Different splits differ in rounding only.  Drops captured graphs.
  */
 pdt_status pdt_problem_set_fx_split(pdt_problem_t problem, int64_t instance, int split);

@@ -214,6 +214,8 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
   // Work of the epilogue that does not depend on the contraction is done here so that its
   // loads overlap the main loop: the regulariser over this workgroup's slice of row
   // pairs, and (when registers allow) O_cur and P of this group's output row.
+  // The slice's row pairs (mm, mm + 1) go to the workgroup's 16-lane groups in turn; a
+  // lane takes columns i, i + 16, ... of both rows, all loaded before they are used.
   double reg = 0.0;
   if (pv.gamma != 0.0 && M > 1) {
     const long long pairs = (long long)(M - 1);
@@ -221,12 +223,20 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
     const long long per = (pairs + W - 1) / W;
     const long long r0 = (long long)wg * per;
     const long long r1 = r0 + per < pairs ? r0 + per : pairs;
-    const long long cnt = (r1 > r0 ? r1 - r0 : 0) * (long long)N;
-    for (long long q = tid; q < cnt; q += 64 * KS) {
-      const long long mm = r0 + q / N;
-      const int n = (int)(q % N);
-      const double e = (double)X[mm * Npad + n] - (double)X[(mm + 1) * Npad + n];
-      reg += e * e;
+#pragma unroll 2
+    for (long long mm = r0 + (tid >> 4); mm < r1; mm += 4 * KS) {
+      const T* __restrict__ xa = X + (size_t)mm * Npad + i;
+      T va[NT], vb[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        va[nt] = xa[16 * nt];
+        vb[nt] = xa[Npad + 16 * nt];
+      }
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const double e = (double)va[nt] - (double)vb[nt];
+        reg += (nt * 16 + i < N) ? e * e : 0.0;
+      }
     }
   }
   const int dd = d0 + 4 * wv + kq;  // epilogue row of this 16-lane group

@@ -502,13 +502,13 @@ void setup_instance(pdt_problem_s* pb, Instance& I, const pdt_problem_desc& d) {
   HIPCHK(launch_setup_anchors(view_of(I), I.mt_aoff, I.anchors, s));
 
   // Forward products of problems with few probe tiles and long photon-number ranges
-  // split each tile's contraction over up to 8 workgroups (about two workgroups per CU
-  // in all, at least 32 64-entry chunks per workgroup).
+  // split each tile's contraction over up to 16 workgroups (about three workgroups per
+  // CU in all, at least 32 64-entry chunks per workgroup).
   int maxch = 0;
   for (size_t t = 0; t < n_dt; ++t)
     if (dt_mhi[t] >= dt_mlo[t]) maxch = std::max(maxch, (dt_mhi[t] - dt_mlo[t]) / kChunkM + 1);
   I.fx_split_auto = 1;
-  if (n_dt < 256) I.fx_split_auto = std::max(1, std::min({8, (int)((512 + n_dt - 1) / n_dt), maxch / 32}));
+  if (n_dt < 256) I.fx_split_auto = std::max(1, std::min({16, (int)((768 + n_dt - 1) / n_dt), maxch / 32}));
   I.fx_count = A.alloc<unsigned>(n_dt);
   HIPCHK(hipMemsetAsync(I.fx_count, 0, n_dt * sizeof(unsigned), s));
   set_fx_split(A, I, I.fx_split_auto);

@@ -124,13 +124,13 @@ def test_split_reduced_precision_paths(dev, precision, tol, kind, which):
 
 
 def test_automatic_choice(dev):
-    # up to 8 workgroups per tile when there are fewer than 256 probe tiles, at least 32
-    # 64-entry chunks per workgroup: 3 tiles of up to ~250 chunks here
+    # up to 16 workgroups per tile when there are fewer than 256 probe tiles (about 768 in
+    # all), at least 32 64-entry chunks per workgroup: 3 tiles of up to ~250 chunks here
     inst = small_instance(M=40000, B=30, D=40, mu_max=36000.0, gamma=1e-4)
     lo, hi = poisson.bands(inst.mu, inst.M, inst.threshold, inst.tail_mode)
     tiles = (inst.D + 15) // 16
     maxch = max((hi[t:t + 16].max() - lo[t:t + 16].min()) // 64 + 1 for t in range(0, inst.D, 16))
-    expected = max(1, min(8, (512 + tiles - 1) // tiles, maxch // 32))
+    expected = max(1, min(16, (768 + tiles - 1) // tiles, maxch // 32))
     pb = _pdt.Problem.from_instance(inst)
     assert expected > 1 and pb.fx_split() == expected
     X = simplex.project_rows(np.random.default_rng(3).normal(size=(inst.M, inst.N)))

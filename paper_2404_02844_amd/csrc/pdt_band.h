@@ -68,7 +68,13 @@ struct Acc<float> {
 // in LDS in a fixed order, then each wave finishes 4 of the 16 probe rows.  Every
 // workgroup also sums the regulariser over a slice of rows.
 // ---------------------------------------------------------------------------------------
-constexpr int PF = 4;   // prefetch depth in contraction steps
+// Prefetch depth in contraction steps of the forward (X rows) and transposed (R rows)
+// products, per MFMA operand type.
+template <typename TC>
+struct Prefetch {
+  static constexpr int fx = sizeof(TC) == 4 ? 8 : 4;
+  static constexpr int ftr = sizeof(TC) == 4 ? 8 : 4;
+};
 // KS (a template parameter, 4 or 8) waves per workgroup split the contraction; the
 // first four waves finish the tile's 16 rows in the epilogues.
 
@@ -199,6 +205,7 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
       }
     }
   }
+  constexpr int PF = Prefetch<TC>::fx;
   TC xb[PF][NTC];
   double rb[PF];
   if (c0 < c1) {
@@ -615,6 +622,7 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
 #pragma unroll
     for (int k = 0; k < NTC; ++k) acc[k] = AccT{0, 0, 0, 0};
     int dc = dlo + kChunkD * (cs0 + wv);
+    constexpr int PF = Prefetch<TC>::ftr;
     TC rb[PF][NTC];
 #pragma unroll
     for (int p = 0; p < PF; ++p) load_r(dc + 16 * kq + p, rb[p], nt0);
@@ -789,22 +797,20 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
 }
 
 
-// two waves per SIMD: the forward product's loads and recursion are latency-bound
-// Workgroups are dispatched in blockIdx order, and the band work of a tile grows with its
+// At least two waves per SIMD: the forward product's loads and recursion are
+// latency-bound.  Workgroups are dispatched in blockIdx order, and the band work of a tile grows with its
 // photon numbers (probe means): the grid runs from the last tile to the first, so the
 // heaviest tiles start first and the light ones fill the tail of the launch.  Each tile
 // still writes its own partials, so the order of every sum is unchanged.
 template <typename TS, typename TC, int NT, int KS>
-__global__ __launch_bounds__(64 * KS) __attribute__((amdgpu_waves_per_eu(2))) void fx_kernel(ProbView pv, Bufs<TS> b,
+__global__ __launch_bounds__(64 * KS, 2) void fx_kernel(ProbView pv, Bufs<TS> b,
                                                                                             SolverState* st, int mode) {
   fx_body<TS, TC, NT, KS>(pv, b, st, mode, gridDim.x - 1 - blockIdx.x, gridDim.x);
 }
 
-// FP32 operands keep three waves per SIMD (the epilogue's batched loads would otherwise
-// raise the register peak of the mixed kernel past that)
 template <typename TS, typename TC, int NT, int KS>
-__global__ __launch_bounds__(64 * KS, (sizeof(TC) == 4 && KS == 4) ? 3 : 1) void ftr_kernel(
-    ProbView pv, Bufs<TS> b, SolverState* st, int mode, double step, int phase) {
+__global__ __launch_bounds__(64 * KS) void ftr_kernel(ProbView pv, Bufs<TS> b, SolverState* st, int mode,
+                                                       double step, int phase) {
   ftr_body<TS, TC, NT, KS>(pv, b, st, mode, step, gridDim.x - 1 - blockIdx.x, phase);
 }
 

@@ -45,7 +45,7 @@ PROFILE_C5 = os.path.join(ROOT, "profiles", "band_kernels_c5_m16384_n129_d19661.
 C2_GOLDEN = os.path.join(ROOT, "tests", "golden", "c2_oracle.json")
 
 
-BAND_SOURCES = ("pdt_band.h", "pdt_device.h", "pdt_pmf.h", "pdt_internal.h", "pdt_tuning.h")
+BAND_SOURCES = ("pdt_band.h", "pdt_decide.h", "pdt_device.h", "pdt_pmf.h", "pdt_internal.h", "pdt_tuning.h")
 
 
 def band_source_sha256() -> str:
@@ -698,7 +698,9 @@ def bench_mega(args, iters=64, workload="c3"):
         tb = (3.0 * M * npad + inst.D * npad) * 8.0
         gbs = tb / times["ftr"] / 1e9
         roof = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
-                "traffic": None, "kernel": "ftr_kernel<double> (F^T R band product + projected step)",
+                "traffic": None,
+                "kernel": "ftr_narrow_kernel<double, double, 10> (F^T R band product + projected step; "
+                          "every row tile meets at most 10 probes)",
                 "per_launch_bytes": tb, "mfma_tflops": achieved, "avg_launch_s": times["ftr"],
                 "fx_avg_launch_s": times["fx"], "iteration_s": times["iteration"],
                 "mixed_ftr_s": times["mixed_ftr"], "mixed_fx_s": times["mixed_fx"],

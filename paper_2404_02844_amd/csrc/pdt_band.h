@@ -223,15 +223,27 @@ __device__ __forceinline__ void fx_body(const ProbView& pv, const Bufs<TS>& b, S
   // pairs, and (when registers allow) O_cur and P of this group's output row.
   // The slice's row pairs (mm, mm + 1) go to the workgroup's 16-lane groups in turn; a
   // lane takes columns i, i + 16, ... of both rows, all loaded before they are used.
+  // After a step (b.regpart) the pairs inside each 16-row tile were summed by the step's
+  // epilogue, one partial per row tile: this workgroup then takes its slice of the pairs
+  // across tile edges, (16 t + 15, 16 t + 16), and its slice of those partials.
   double reg = 0.0;
+  const bool edges = iter && b.regpart;
   if (pv.gamma != 0.0 && M > 1) {
-    const long long pairs = (long long)(M - 1);
+    const long long nmt = (M + 15) / 16;
+    const long long pairs = edges ? nmt - 1 : (long long)(M - 1);
     const long long W = nwg;
     const long long per = (pairs + W - 1) / W;
     const long long r0 = (long long)wg * per;
     const long long r1 = r0 + per < pairs ? r0 + per : pairs;
+    if (edges) {
+      const long long pt = (nmt + W - 1) / W;
+      const long long q0 = (long long)wg * pt;
+      const long long q1 = q0 + pt < nmt ? q0 + pt : nmt;
+      for (long long t = q0 + tid; t < q1; t += 64 * KS) reg += b.regpart[t];
+    }
 #pragma unroll 2
-    for (long long mm = r0 + (tid >> 4); mm < r1; mm += 4 * KS) {
+    for (long long q = r0 + (tid >> 4); q < r1; q += 4 * KS) {
+      const long long mm = edges ? 16 * q + 15 : q;
       const T* __restrict__ xa = X + (size_t)mm * Npad + i;
       T va[NT], vb[NT];
 #pragma unroll
@@ -708,6 +720,10 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
     T tau[1];
     simplex_threshold<T, 16, NT, 1, 8>(z, tau);
     double rr = 0.0;  // this row's gradient-restart term, sum_n (Y - X_new)(X_new - X_cur) / w_m
+    // the regulariser's row pairs inside the tile are summed here from the new rows (each
+    // group's row replaces its gradient row in S: only that group reads or writes it)
+    const bool regp = b.regpart && pv.gamma != 0.0 && M > 1;
+    const int r = 4 * wv + kq;
     if (mval) {
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
@@ -716,6 +732,7 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
         Xn[(size_t)m * Npad + n] = xn;
         if constexpr (delta) b.dX[(size_t)m * Npad + n] = (float)(xn - xcs[nt]);
         if (n < N) rr += ((double)ys[nt] - (double)xn) * ((double)xn - (double)xcs[nt]);
+        if (regp) S[r * LDT + n] = (double)xn;
       }
       if (b.wrow) rr /= b.wrow[m];
     }
@@ -728,6 +745,32 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
 #pragma unroll
         for (int w = 0; w < KS; ++w) sr += red[w];
         b.rpart[mt] = sr;
+      }
+    }
+    if (regp) {
+      // pairs (m, m + 1) with both rows in this tile; the pair across the tile's lower edge
+      // is the forward product's
+      __shared__ double regred[KS];
+      __syncthreads();
+      double rs = 0.0;
+      if (mval && r < 15 && m + 1 < M) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int n = nt * 16 + i;
+          if (n < N) {
+            const double e = S[r * LDT + n] - S[(r + 1) * LDT + n];
+            rs += e * e;
+          }
+        }
+      }
+      rs = group_sum<64>(rs);
+      if (lane == 0) regred[wv] = rs;
+      __syncthreads();
+      if (tid == 0) {
+        double sg = 0.0;
+#pragma unroll
+        for (int w = 0; w < KS; ++w) sg += regred[w];
+        b.regpart[mt] = sg;
       }
     }
   } else {

@@ -139,6 +139,7 @@ struct Instance {
   double* partials = nullptr;
   int n_partials = 0;
   double* rpart = nullptr;  // [ceil(M / 16)] gradient-restart partials of the step
+  double* regpart = nullptr;  // [ceil(M / 16)] in-tile regulariser sums of the step's iterate
   SolverState* st = nullptr;
   SolverState* st_eval = nullptr;
   double* scalar = nullptr;
@@ -296,6 +297,7 @@ Bufs<T> bufs_of(const Instance& I, const Work<T>& w, double* history, const doub
     b.R32_rej = w.R32_rej;
   }
   if (restart == PDT_RESTART_GRADIENT) b.rpart = I.rpart;
+  b.regpart = I.regpart;
   return b;
 }
 
@@ -522,6 +524,8 @@ void setup_instance(pdt_problem_s* pb, Instance& I, const pdt_problem_desc& d) {
   I.n_partials = (int)std::max(n_dt * (kMaxFxSplit + 1), 2 * n_mt);
   I.partials = A.alloc<double>(I.n_partials);
   I.rpart = A.alloc<double>(n_mt);
+  I.regpart = A.alloc<double>(n_mt);
+  HIPCHK(hipMemsetAsync(I.regpart, 0, n_mt * sizeof(double), s));
   I.st = A.alloc<SolverState>(1);
   I.st_eval = A.alloc<SolverState>(1);
   I.scalar = A.alloc<double>(4);

@@ -110,6 +110,10 @@ struct Bufs {
                                  // Hessian products of a conjugate-gradient solve that stopped)
   double* rpart = nullptr;       // [ceil(M / 16)] gradient-restart partials, one per row tile,
                                  // written by the step (null: function restart only)
+  double* regpart = nullptr;     // [ceil(M / 16)] the new iterate's regulariser sums over the row
+                                 // pairs inside each 16-row tile, written by the step and read
+                                 // by the forward product of the same iteration (null: the
+                                 // forward product sums every pair itself)
   float* R32_acc = nullptr;      // [D][Npad] FP32 copies of R_acc / R_rej (mixed path): every
   float* R32_rej = nullptr;      // forward-product epilogue that writes R writes them too, and
                                  // the FP32-operand transposed product reads them instead of R

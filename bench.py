@@ -131,7 +131,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-c2", action="store_true", help="c5: leave out the M=4096 figures")
+    ap.add_argument("--no-c2", action="store_true", help="c5: leave out the M=4096 and M=64 figures")
     ap.add_argument("--tol", type=float, default=None,
                     help="relative objective tolerance (default: 1e-8 for c5, 1e-9 for c2)")
     ap.add_argument("--workload", default="c5", choices=["c5", "c2", "c3", "c4", "loop"],
@@ -360,6 +360,31 @@ def stats(vals, seed=0):
             "ci95_median": [float(np.percentile(boots, 2.5)), float(np.percentile(boots, 97.5))]}
 
 
+def c1_leg(iters=2000, reps=5):
+    """The M=64 workload's absolute time for 2000 FP64 iterations (uniform step 1/L_hat,
+    function restart, from Pi = 1/N: the trajectory the parity tests compare with the
+    oracle), median of `reps` solves after one untimed solve."""
+    import torch
+    from paper_2404_02844_amd import _pdt, synth
+    inst = synth.c1_small()
+    pb = _pdt.Problem.from_instance(inst)
+    Pi = torch.zeros((inst.M, inst.N), dtype=torch.float64, device="cuda")
+    pb.solve(Pi, max_iters=iters)
+    walls = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = pb.solve(Pi, max_iters=iters)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t)
+    pb.close()
+    w = float(np.median(walls))
+    out = {"workload": inst.name, "M": inst.M, "N": inst.N, "D": inst.D, "iters": int(info["iters"]),
+           "time_s": w, "us_per_iteration": w / iters * 1e6, "objective": info["objective"]}
+    log(f"[bench] c1: {out}")
+    return out
+
+
 def c2_leg(tol=1e-9, reps=3):
     """The M=4096 workload's figures for the default line: the FP64, mixed and FP32 (with
     refinement) solves to 1e-9 against a reference optimum, which is checked against the
@@ -521,6 +546,7 @@ def bench_c5(args):
                  "fell_back": int(sum(r["warm_mixed"]["fell_back_to_cold"] for r in rows)),
                  "rows": rows}
     c2 = None if args.no_c2 else c2_leg()
+    c1 = None if args.no_c2 else c1_leg()
     cpu = None
     if not args.no_cpu:
         from paper_2404_02844_amd import warmstart as ws
@@ -558,6 +584,7 @@ def bench_c5(args):
                                            "targets_unconverged", "epochs", "loss_last")},
         "study": study,
         "c2": c2,
+        "c1": c1,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

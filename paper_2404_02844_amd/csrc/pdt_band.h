@@ -655,11 +655,15 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
 #pragma unroll
       for (int j = 0; j < 16; ++j) Ft[wv][lane][j] = vals[j];
       wave_lds_order();
+      // the chunk's 16 A operands are read back at once, so no step waits on LDS
+      TC av[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) av[s] = (TC)Ft[wv][16 * kq + s][i];
       // the next chunk's F values are generated between this chunk's MFMAs
       Gen g = gn;
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
-        const TC a = (TC)Ft[wv][16 * kq + s][i];
+        const TC a = av[s];
 #pragma unroll
         for (int k = 0; k < NTC; ++k)
           if (NPASS == 1 || nt0 + k < NT) acc[k] = Acc<TC>::mfma(a, rb[s % PF][k], acc[k]);

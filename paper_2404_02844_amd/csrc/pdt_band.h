@@ -461,9 +461,10 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
   constexpr int NPASS = (NT + NTC - 1) / NTC;
   // the F^T staging tiles of the main loop and the reduction tile share one LDS block
   // (a single pass), or sit side by side (two passes)
-  constexpr int kFt = NW ? 0 : KS * kChunkD * 17, kS = 16 * LDT;
+  // F^T staging in the MFMA operand type (doubles of LDS per wave: 64 x 17 operands)
+  constexpr int kFt = NW ? 0 : (KS * kChunkD * 17 * (int)sizeof(TC) + 7) / 8, kS = 16 * LDT;
   __shared__ double lds[NPASS > 1 ? kFt + kS : (kFt > kS ? kFt : kS)];
-  double(*Ft)[kChunkD][17] = reinterpret_cast<double(*)[kChunkD][17]>(lds);
+  TC(*Ft)[kChunkD][17] = reinterpret_cast<TC(*)[kChunkD][17]>(lds);
   double* S = NPASS > 1 ? lds + kFt : lds;
   __shared__ double red[KS];
 
@@ -653,12 +654,12 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
     for (int rd = 0; rd < rounds; ++rd, dc += stride) {
       const int dcn = dc + stride;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) Ft[wv][lane][j] = vals[j];
+      for (int j = 0; j < 16; ++j) Ft[wv][lane][j] = (TC)vals[j];
       wave_lds_order();
       // the chunk's 16 A operands are read back at once, so no step waits on LDS
       TC av[16];
 #pragma unroll
-      for (int s = 0; s < 16; ++s) av[s] = (TC)Ft[wv][16 * kq + s][i];
+      for (int s = 0; s < 16; ++s) av[s] = Ft[wv][16 * kq + s][i];
       // the next chunk's F values are generated between this chunk's MFMAs
       Gen g = gn;
 #pragma unroll

@@ -536,51 +536,63 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
   };
 
 
-  // The epilogue's inputs that do not depend on the contraction -- Y = X + beta (X -
-  // X_prev) and its Laplacian along m for this group's row -- are loaded and formed here,
-  // so that their load latency overlaps the main loop (held in registers when the tile
-  // is narrow enough to leave room for them).
   const int m = m0 + 4 * wv + kq;  // epilogue row of this 16-lane group
   const bool mval = wv < 4 && m < M;
   const T beta = (T)st->beta;
   const T* __restrict__ Xc = b.X[st->ix_cur];
   const T* __restrict__ Xp = b.X[st->ix_prev];
-  // All 6 NT loads (rows m-1, m, m+1 of both iterates; rows clamped into [0, M-1],
-  // padding columns read and discarded) are issued before any of them is used, so the
-  // group waits for memory once, not once per column tile.
+  // Y = X + beta (X - X_prev) for the Laplacian along m: each 16-lane group loads its own
+  // row of both iterates (the tile's first and last group also the row just outside the
+  // tile), all column tiles before any is used.  Rows r - 1 and r + 1 of the same wave
+  // are lanes -16 / +16 (shuffles); a wave's first and last rows and the two outside rows
+  // pass through LDS (Yb: 2 rows per wave, then rows m0 - 1 and m0 + 16).
+  __shared__ double Yb[10 * LDT];
   auto form_y = [&](T (&xc)[NT], T (&y)[NT], T (&ly)[NT]) {
     const int mc = m < M - 1 ? m : M - 1;
     const size_t r0 = (size_t)mc * Npad + i;
-    const size_t rm = mc > 0 ? r0 - Npad : r0;
-    const size_t rq = mc < M - 1 ? r0 + Npad : r0;
-    T a[NT], ap[NT], am[NT], amp[NT], aq[NT], aqp[NT];
+    const bool lo_h = wv == 0 && kq == 0 && m0 > 0;
+    const bool hi_h = wv == 3 && kq == 3 && m0 + 16 < M;
+    const size_t rh = (size_t)(lo_h ? m0 - 1 : (hi_h ? m0 + 16 : mc)) * Npad + i;
+    T a[NT], ap[NT], h[NT], hp[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       a[nt] = Xc[r0 + 16 * nt];
       ap[nt] = Xp[r0 + 16 * nt];
-      am[nt] = Xc[rm + 16 * nt];
-      amp[nt] = Xp[rm + 16 * nt];
-      aq[nt] = Xc[rq + 16 * nt];
-      aqp[nt] = Xp[rq + 16 * nt];
     }
+    if (lo_h || hi_h) {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        h[nt] = Xc[rh + 16 * nt];
+        hp[nt] = Xp[rh + 16 * nt];
+      }
+    }
+    T up[NT], dn[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const T yy = a[nt] + beta * (a[nt] - ap[nt]);
+      y[nt] = yy;
+      up[nt] = __shfl(yy, (lane + 48) & 63);
+      dn[nt] = __shfl(yy, (lane + 16) & 63);
+      if (wv < 4 && (kq == 0 || kq == 3)) Yb[(2 * wv + (kq == 3)) * LDT + 16 * nt + i] = (double)yy;
+      if (lo_h || hi_h) Yb[(lo_h ? 8 : 9) * LDT + 16 * nt + i] = (double)(h[nt] + beta * (h[nt] - hp[nt]));
+    }
+    __syncthreads();
+    const int rup = wv > 0 ? 2 * wv - 1 : 8;  // Yb row of row 4 wv - 1
+    const int rdn = wv < 3 ? 2 * wv + 2 : 9;  // Yb row of row 4 wv + 4
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const bool v = mval && nt * 16 + i < N;
-      const T yy = a[nt] + beta * (a[nt] - ap[nt]);
-      const T lm = m > 0 ? yy - (am[nt] + beta * (am[nt] - amp[nt])) : (T)0;
-      const T lq = m < M - 1 ? yy - (aq[nt] + beta * (aq[nt] - aqp[nt])) : (T)0;
+      const T yy = y[nt];
+      const T ym = kq > 0 ? up[nt] : (wv < 4 ? (T)Yb[rup * LDT + 16 * nt + i] : (T)0);
+      const T yq = kq < 3 ? dn[nt] : (wv < 4 ? (T)Yb[rdn * LDT + 16 * nt + i] : (T)0);
+      const T lm = m > 0 ? yy - ym : (T)0;
+      const T lq = m < M - 1 ? yy - yq : (T)0;
       xc[nt] = v ? a[nt] : (T)0;
       y[nt] = v ? yy : (T)0;
       ly[nt] = v ? lm + lq : (T)0;
     }
   };
-  // (a split tile's epilogue runs in one of its workgroups, found only at the end)
-  constexpr bool kHoist = NT >= 4 && NT <= 5;
-  const bool hoist = kHoist && phase == FTR_FUSED;
   T hx[NT], hy[NT], hly[NT];
-  if constexpr (kHoist) {
-    if (mode == FTR_STEP && hoist) form_y(hx, hy, hly);
-  }
 
   // Narrow probe ranges (at most kNarrowD probes: the thin row tiles of sparse, wide
   // bands, e.g. mu_d = d^2) skip the 64-probe chunks.  Contraction step q takes probes
@@ -708,7 +720,7 @@ __device__ __forceinline__ void ftr_body(const ProbView& pv, const Bufs<TS>& b, 
     constexpr bool delta = !std::is_same<TS, TC>::value;
     T z[1][NT];
     T xcs[NT], ys[NT];
-    if (!(kHoist && hoist)) form_y(hx, hy, hly);
+    form_y(hx, hy, hly);
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const int n = nt * 16 + i;

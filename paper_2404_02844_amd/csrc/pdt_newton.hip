@@ -106,7 +106,7 @@ __device__ __forceinline__ double sum_partials(const double* part, int nb) {
   for (int m = wave0; m < (r).M; m += nwaves)
 
 // ---- KKT residual with the clamped multiplier, and the residual w of the binding-set
-// tolerance eps = min(1e-3, w) ------------------------------------------------------------
+// tolerance eps = min(cap, w) (cap: the eps_cap option, 1e-9 by default) ------------------
 template <int V>
 __global__ __launch_bounds__(256) void nt_measure_kernel(NtRows r, const double* X, const double* G, double* part) {
   double acc[2] = {0.0, 0.0};

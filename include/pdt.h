@@ -264,6 +264,8 @@ pdt_status pdt_problem_scaling(pdt_problem_t problem, double* hdiag, double* lip
  * picks 8 for launches with few tiles (see pdt_tuning.h).  The waves' partial results
  * are summed in a fixed order, so a given shape is deterministic, while the two shapes
  * differ in rounding.  Changing the shape drops captured graphs and the batch plan.
+ * A problem whose 16-row tiles all meet fewer than 32 probes runs its transposed product
+ * as a dedicated four-wave launch without chunk staging (its ks_ftr is not used).
  */
 pdt_status pdt_problem_set_tiles(pdt_problem_t problem, int64_t instance, int precision, int ks_fx, int ks_ftr);
 /* The shape in effect (host int* outputs, nullable). */

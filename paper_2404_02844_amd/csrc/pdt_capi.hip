@@ -1916,6 +1916,10 @@ void build_plan(pdt_problem_s* pb, int scaling, int restart, const std::vector<d
     bi.pv = view_var(I, var);
     bi.pv.fx_split = 1;  // batches run one workgroup per probe tile and per row tile
     bi.pv.ftr_split = 1;
+    // a problem whose row tiles are all narrow runs its single solves' transposed product
+    // with four waves (the narrow-only launch): the batch uses the same shape, so the
+    // narrow contraction splits and sums its steps in the same order
+    if (bi.pv.ftr_narrow_all) bi.pv.ks_ftr = 4;
     bi.b = bufs_of(I, work_of<T>(I), nullptr, scaling == PDT_STEP_DIAG ? I.wrow : nullptr, false, restart);
     bi.b.fx_part = nullptr;
     bi.b.fx_count = nullptr;

@@ -46,6 +46,27 @@ def test_batch_equals_single_solves(dev, precision):
         assert info["objective"] == single["objective"]
 
 
+@pytest.mark.parametrize("precision", [_pdt.PDT_FP64, _pdt.PDT_FP32])
+def test_batch_with_narrow_tiles_equals_single_solves(dev, precision):
+    # few probes with wide bands: every 16-row tile meets only a few probes, so the single
+    # solve runs the narrow-only transposed product; the batch must reproduce it bit for bit
+    wide = [synth.make_instance(f"narrow_{k}", M=1500 + 500 * k, B=20 + 5 * k, eta=0.8, dark=1e-4, D=30 + 10 * k,
+                                mu_max=1300.0 + 400 * k, shots=1e6, gamma=1e-4, tail_mode=synth.LUMP,
+                                threshold=1e-16, rng=synth.rng_for(61, spawn=k)) for k in range(2)]
+    insts = wide + family(count=2)
+    bp = _pdt.BatchProblem(insts)
+    Pis = [torch.zeros((i.M, i.N), dtype=torch.float64, device=dev) for i in insts]
+    infos = bp.solve(Pis, precision=precision, max_iters=300)
+    for inst, Pi, info in zip(insts, Pis, infos):
+        pb = _pdt.Problem.from_instance(inst)
+        X = torch.zeros_like(Pi)
+        single = pb.solve(X, precision=precision, max_iters=300)
+        assert info["iters"] == single["iters"] == 300
+        assert torch.equal(Pi, X), inst.name
+        assert info["objective"] == single["objective"]
+        pb.close()
+
+
 def test_batch_matches_oracle_and_stops_per_instance(dev):
     insts = family(count=5)
     bp = _pdt.BatchProblem(insts)

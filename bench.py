@@ -670,6 +670,13 @@ def bench_batch(args, count=256, iters=2000):
         infos = bp.solve(Pis, precision=_pdt.PDT_FP32, max_iters=iters, scaling=_pdt.PDT_STEP_DIAG)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / args.steps
+    # the same 2000 iterations with every instance kept in FP32 (no promotion of a
+    # stalled instance to the FP64 refinement): the products' own throughput
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    bp.solve(Pis, precision=_pdt.PDT_FP32, max_iters=iters, scaling=_pdt.PDT_STEP_DIAG, skip_refine=True)
+    torch.cuda.synchronize()
+    el32 = time.perf_counter() - t1
     elems = sum(i.M * i.N for i in insts)
     out = {
         "metric": METRIC, "value": elems * iters / el, "unit": "POVM-elem*iters/s", "n_gpus": 1,
@@ -680,6 +687,8 @@ def bench_batch(args, count=256, iters=2000):
                    "N_range": [min(i.N for i in insts), max(i.N for i in insts)],
                    "step": "row-scaled (Hessian diagonal)"},
         "instances_per_s": count / el,
+        "fp64_refinement_iters_mean": float(np.mean([i["refine_iters"] for i in infos])),
+        "fp32_only": {"s_per_step": el32, "instances_per_s": count / el32, "elem_iters_per_s": elems * iters / el32},
         "objective_range": [min(i["objective"] for i in infos), max(i["objective"] for i in infos)],
     }
     print(json.dumps(out), flush=True)
